@@ -1,0 +1,756 @@
+/*
+ * esdg_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH.
+ *
+ * A plain, slow, FP64 CPU statement of the entropy-stable DGSEM right-hand
+ * side R(q) for the 3-D compressible Euler equations with gravity (and an
+ * f-plane Coriolis source) on a uniform box of affine hexahedra with
+ * Legendre-Gauss-Lobatto (LGL) nodes, the Carpenter-Kennedy LSRK(5,4)
+ * time step, and the entropy / conservation diagnostics.
+ *
+ * Only tests/, __graft_entry__.smoke() and the cpu_baseline leg of bench.py
+ * load this library.  It shares no source, table or constant with the HIP
+ * library: every quantity below is computed here from its definition.
+ *
+ * Paper references (Waterhouse, Waruszewski, Wilcox, Warburton, Giraldo,
+ * "GPU Performance of an Entropy-Stable Discontinuous Galerkin Euler Solver
+ * with Non-Conservative Terms"):
+ *   - governing equations, total energy with geopotential, pressure:
+ *     Sec. 2, Eqs. (Eq:euler) and the pressure definition that follows;
+ *   - semi-discrete form: Sec. 3, Eq. (nm:semi) and the operator list after
+ *     it (G, D, F, F*, M, M^s); the printed equation is read as the
+ *     Jacobian-weighted skew (flux-differencing) form, see rhs_element();
+ *   - averages, log-mean, jump and the momentum flux with the gravity term
+ *     rho_hat [[phi]]/2: Sec. 4.1 (GPU optimizations), the displayed
+ *     definitions of {{a}}, {{a}}_log, [[a]] and of the momentum flux;
+ *   - Horner-series log-mean with per-node logarithms: Sec. 4.1 text;
+ *   - LSRK(5,4) time stepping: Sec. 3, last paragraph.
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - mass/energy components of the entropy-conservative flux: Ranocha-type
+ *     flux, with {{phi}} f^rho added to the energy flux because E contains
+ *     rho*phi, and p* = {{p}};
+ *   - log-mean series branch: u = ((b-a)/(b+a))^2 < 1e-4 uses
+ *     (a+b) / (2 + u(2/3 + u(2/5 + u 2/7))), else (b-a)/(ln b - ln a);
+ *   - face flux: entropy-conservative flux plus Rusanov (local Lax-Friedrichs)
+ *     dissipation 0.5*lambda*(q+ - q-), lambda = max over both sides of
+ *     |u.n| + c; ESDG_SURF_EC drops the dissipation;
+ *   - reflecting walls: mirror state (rho, m - 2 (m.n) n, E), phi+ = phi-;
+ *   - Coriolis: f-plane, h = (0, f m_y, -f m_x, 0, 0);
+ *   - time step: dt = CFL / ((N+1) max_a sum_r (|u_r| + c) / h_r).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NQMAX 16
+#define SURF_RUSANOV 0
+#define SURF_EC 1
+#define TERM_VOL 1
+#define TERM_FACE 2
+#define TERM_SRC 4
+
+typedef struct {
+    int N, Nq, Np;
+    int K[3];
+    int periodic[3];
+    int surf;
+    double lo[3], hi[3], h[3];
+    double gamma, gas_R, grav, cor_f;
+    double xi[NQMAX], w[NQMAX];
+    double D[NQMAX][NQMAX];
+    double S[NQMAX][NQMAX]; /* S = W D - (W D)^T, skew */
+    int64_t ne, nn;
+    double *xyz; /* [e][3][Np] node coordinates */
+    double *phi; /* [e][Np] geopotential at the nodes */
+} omesh;
+
+/* ------------------------------------------------------------------------ */
+/* LGL nodes, weights and differentiation matrix (textbook definitions)      */
+/* ------------------------------------------------------------------------ */
+
+/* Legendre P_n(x) and P_{n-1}(x) by the three-term recurrence. */
+static void legendre_pair(int n, long double x, long double *pn, long double *pnm1)
+{
+    long double p0 = 1.0L, p1 = x;
+    if (n == 0) { *pn = 1.0L; *pnm1 = 0.0L; return; }
+    for (int k = 2; k <= n; ++k) {
+        long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    *pn = p1;
+    *pnm1 = p0;
+}
+
+/* LGL nodes are -1, +1 and the N-1 roots of P_N'(x).  Interior roots by
+ * Newton's method on P_N' using P_N'' from the Legendre ODE
+ * (1-x^2) P'' = 2x P' - N(N+1) P, started at Chebyshev-Lobatto points.
+ * Weights w_i = 2 / (N(N+1) P_N(x_i)^2).  D_ij = P_N(x_i)/(P_N(x_j)(x_i-x_j))
+ * for i != j, D_00 = -N(N+1)/4, D_NN = N(N+1)/4, other diagonals 0. */
+void oracle_lgl(int N, double *x, double *w, double *D)
+{
+    int Nq = N + 1;
+    long double X[NQMAX];
+    X[0] = -1.0L;
+    X[N] = 1.0L;
+    for (int i = 1; i < N; ++i) {
+        long double t = -cosl(3.14159265358979323846264338327950288L * i / N);
+        for (int it = 0; it < 100; ++it) {
+            long double pn, pnm1;
+            legendre_pair(N, t, &pn, &pnm1);
+            /* P_N'(t) = N (t P_N - P_{N-1}) / (t^2 - 1) */
+            long double dp = N * (t * pn - pnm1) / (t * t - 1.0L);
+            long double d2p = (2.0L * t * dp - N * (N + 1.0L) * pn) / (1.0L - t * t);
+            long double dt = dp / d2p;
+            t -= dt;
+            if (fabsl(dt) < 1e-19L) break;
+        }
+        X[i] = t;
+    }
+    /* exact symmetry of the node set */
+    for (int i = 0; i < Nq / 2; ++i) {
+        long double s = 0.5L * (X[N - i] - X[i]);
+        X[N - i] = s;
+        X[i] = -s;
+    }
+    if (N % 2 == 0) X[N / 2] = 0.0L;
+    long double P[NQMAX];
+    for (int i = 0; i < Nq; ++i) {
+        long double pnm1;
+        legendre_pair(N, X[i], &P[i], &pnm1);
+        x[i] = (double)X[i];
+        w[i] = (double)(2.0L / (N * (N + 1.0L) * P[i] * P[i]));
+    }
+    for (int i = 0; i < Nq; ++i)
+        for (int j = 0; j < Nq; ++j) {
+            long double v;
+            if (i != j) v = P[i] / (P[j] * (X[i] - X[j]));
+            else if (i == 0) v = -N * (N + 1.0L) / 4.0L;
+            else if (i == N) v = N * (N + 1.0L) / 4.0L;
+            else v = 0.0L;
+            D[i * Nq + j] = (double)v;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh                                                                      */
+/* ------------------------------------------------------------------------ */
+
+static inline int64_t elem_index(const omesh *m, int ex, int ey, int ez)
+{
+    return ex + (int64_t)m->K[0] * (ey + (int64_t)m->K[1] * ez);
+}
+
+/* Vertex d-coordinate of element boundary e (0..K): lo + (hi-lo)*e/K. */
+static double vertex(const omesh *m, int d, int e)
+{
+    return m->lo[d] + (m->hi[d] - m->lo[d]) * ((double)e / (double)m->K[d]);
+}
+
+void *oracle_mesh_create(int N, const int *K, const double *lo, const double *hi,
+                         const int *periodic, double gamma, double gas_R, double grav,
+                         double cor_f, int surf)
+{
+    if (N < 1 || N >= NQMAX) return NULL;
+    for (int d = 0; d < 3; ++d)
+        if (K[d] < 1 || !(hi[d] > lo[d])) return NULL;
+    omesh *m = (omesh *)calloc(1, sizeof(omesh));
+    if (!m) return NULL;
+    m->N = N;
+    m->Nq = N + 1;
+    m->Np = m->Nq * m->Nq * m->Nq;
+    for (int d = 0; d < 3; ++d) {
+        m->K[d] = K[d];
+        m->lo[d] = lo[d];
+        m->hi[d] = hi[d];
+        m->periodic[d] = periodic[d] ? 1 : 0;
+        m->h[d] = (hi[d] - lo[d]) / K[d];
+    }
+    m->gamma = gamma;
+    m->gas_R = gas_R;
+    m->grav = grav;
+    m->cor_f = cor_f;
+    m->surf = surf;
+    double Dm[NQMAX * NQMAX];
+    oracle_lgl(N, m->xi, m->w, Dm);
+    for (int i = 0; i < m->Nq; ++i)
+        for (int j = 0; j < m->Nq; ++j) m->D[i][j] = Dm[i * m->Nq + j];
+    for (int i = 0; i < m->Nq; ++i)
+        for (int j = 0; j < m->Nq; ++j)
+            m->S[i][j] = m->w[i] * m->D[i][j] - m->w[j] * m->D[j][i];
+    m->ne = (int64_t)K[0] * K[1] * K[2];
+    m->nn = m->ne * m->Np;
+    m->xyz = (double *)malloc(sizeof(double) * 3 * m->nn);
+    m->phi = (double *)malloc(sizeof(double) * m->nn);
+    if (!m->xyz || !m->phi) {
+        free(m->xyz);
+        free(m->phi);
+        free(m);
+        return NULL;
+    }
+    const int Nq = m->Nq, Np = m->Np;
+    for (int ez = 0; ez < K[2]; ++ez)
+        for (int ey = 0; ey < K[1]; ++ey)
+            for (int ex = 0; ex < K[0]; ++ex) {
+                int64_t e = elem_index(m, ex, ey, ez);
+                int ee[3] = {ex, ey, ez};
+                double XL[3], XR[3];
+                for (int d = 0; d < 3; ++d) {
+                    XL[d] = vertex(m, d, ee[d]);
+                    XR[d] = vertex(m, d, ee[d] + 1);
+                }
+                for (int k = 0; k < Nq; ++k)
+                    for (int j = 0; j < Nq; ++j)
+                        for (int i = 0; i < Nq; ++i) {
+                            int n = i + Nq * (j + Nq * k);
+                            int ii[3] = {i, j, k};
+                            for (int d = 0; d < 3; ++d) {
+                                double s = m->xi[ii[d]];
+                                /* affine map from the shared vertices: the face
+                                 * nodes of two neighbours coincide bitwise */
+                                double x = 0.5 * (1.0 - s) * XL[d] + 0.5 * (1.0 + s) * XR[d];
+                                m->xyz[(e * 3 + d) * Np + n] = x;
+                            }
+                            m->phi[e * Np + n] = grav * m->xyz[(e * 3 + 2) * Np + n];
+                        }
+            }
+    return m;
+}
+
+void oracle_mesh_destroy(void *mp)
+{
+    omesh *m = (omesh *)mp;
+    if (!m) return;
+    free(m->xyz);
+    free(m->phi);
+    free(m);
+}
+
+int64_t oracle_mesh_nelem(void *mp) { return ((omesh *)mp)->ne; }
+
+void oracle_node_coords(void *mp, double *xyz)
+{
+    omesh *m = (omesh *)mp;
+    memcpy(xyz, m->xyz, sizeof(double) * 3 * m->nn);
+}
+
+void oracle_get_phi(void *mp, double *phi)
+{
+    omesh *m = (omesh *)mp;
+    memcpy(phi, m->phi, sizeof(double) * m->nn);
+}
+
+/* Replace the nodal geopotential (used to test entropy conservation with a
+ * gravity term on a fully periodic box, where phi = g z is not periodic). */
+void oracle_set_phi(void *mp, const double *phi)
+{
+    omesh *m = (omesh *)mp;
+    memcpy(m->phi, phi, sizeof(double) * m->nn);
+}
+
+void oracle_tables(void *mp, double *xi, double *w, double *D, double *S)
+{
+    omesh *m = (omesh *)mp;
+    for (int i = 0; i < m->Nq; ++i) {
+        xi[i] = m->xi[i];
+        w[i] = m->w[i];
+        for (int j = 0; j < m->Nq; ++j) {
+            D[i * m->Nq + j] = m->D[i][j];
+            S[i * m->Nq + j] = m->S[i][j];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pointwise physics                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Pressure from the conservative state, with E containing rho*phi:
+ * P = (gamma-1) (E - |U|^2/(2 rho) - rho phi)   (Sec. 2). */
+static double pressure(const double q[5], double phi, double gamma)
+{
+    double ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+    return (gamma - 1.0) * (q[4] - ke - q[0] * phi);
+}
+
+/* Logarithmic mean {{a}}_log = [[a]] / [[ln a]] (Sec. 4.1), with the
+ * near-equal branch by the Taylor series of 2 atanh(f)/f in u = f^2,
+ * f = (b-a)/(b+a). */
+double oracle_logmean(double a, double b)
+{
+    double f = (b - a) / (b + a);
+    double u = f * f;
+    if (u < 1e-4)
+        return (a + b) / (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0))));
+    return (b - a) / (log(b) - log(a));
+}
+
+/* Physical Euler flux in direction r (conservative form of Eq:euler). */
+void oracle_euler_flux(int r, const double q[5], double phi, double gamma, double f[5])
+{
+    double p = pressure(q, phi, gamma);
+    double ur = q[1 + r] / q[0];
+    f[0] = q[1 + r];
+    for (int c = 0; c < 3; ++c) f[1 + c] = q[1 + c] * ur + (c == r ? p : 0.0);
+    f[4] = (q[4] + p) * ur;
+}
+
+/* Two-point volume flux F_r(a, b) for own node a and partner b.
+ * Mass and momentum follow the paper's momentum flux
+ *   f^m_c = f^rho {{u_c}} + delta_cr (p* + rho_hat [[phi]] / 2),
+ *   rho_hat = {{b}} {{rho}}_log / b_a,  b = rho / (2 p)   (Sec. 4.1)
+ * with f^rho = {{rho}}_log {{u_r}} and p* = {{p}}; the energy flux is the
+ * Ranocha-type form plus {{phi}} f^rho (E contains rho*phi).  The result is
+ * not symmetric in (a, b) because of the gravity term. */
+void oracle_two_point_flux(int r, const double qa[5], const double qb[5], double phia,
+                           double phib, double gamma, double F[5])
+{
+    double ra = qa[0], rb = qb[0];
+    double ua[3], ub[3];
+    for (int c = 0; c < 3; ++c) {
+        ua[c] = qa[1 + c] / ra;
+        ub[c] = qb[1 + c] / rb;
+    }
+    double pa = pressure(qa, phia, gamma), pb = pressure(qb, phib, gamma);
+    double rho_ln = oracle_logmean(ra, rb);
+    double z_ln = oracle_logmean(ra / pa, rb / pb); /* {{rho/p}}_log */
+    double ba = ra / (2.0 * pa), bb = rb / (2.0 * pb);
+    double frho = rho_ln * 0.5 * (ua[r] + ub[r]);
+    double rho_hat = 0.5 * (ba + bb) * rho_ln / ba;
+    double grav_term = 0.5 * rho_hat * (phib - phia);
+    double pmean = 0.5 * (pa + pb);
+    F[0] = frho;
+    for (int c = 0; c < 3; ++c)
+        F[1 + c] = frho * 0.5 * (ua[c] + ub[c]) + (c == r ? pmean + grav_term : 0.0);
+    double uaub = ua[0] * ub[0] + ua[1] * ub[1] + ua[2] * ub[2];
+    F[4] = frho * (1.0 / ((gamma - 1.0) * z_ln) + 0.5 * uaub + 0.5 * (phia + phib)) +
+           0.5 * (pa * ub[r] + pb * ua[r]);
+}
+
+/* Normal face flux F* . n for the face with outward normal n = s e_r (s = +-1):
+ * s f_r(q-, q+) - lambda/2 (q+ - q-) with lambda = max(|u.n| + c) (Rusanov),
+ * or without dissipation for the entropy-conservative face flux. */
+void oracle_surface_flux(int r, int s, const double qm[5], const double qp[5], double phim,
+                         double phip, double gamma, int surf, double Fn[5])
+{
+    double F[5];
+    oracle_two_point_flux(r, qm, qp, phim, phip, gamma, F);
+    double lam = 0.0;
+    if (surf == SURF_RUSANOV) {
+        double pm = pressure(qm, phim, gamma), pp = pressure(qp, phip, gamma);
+        double cm = sqrt(gamma * pm / qm[0]), cp = sqrt(gamma * pp / qp[0]);
+        double lm = fabs(qm[1 + r] / qm[0]) + cm;
+        double lp = fabs(qp[1 + r] / qp[0]) + cp;
+        lam = lm > lp ? lm : lp;
+    }
+    for (int v = 0; v < 5; ++v) Fn[v] = s * F[v] - 0.5 * lam * (qp[v] - qm[v]);
+}
+
+/* Entropy variables of eta = -rho s/(gamma-1), s = ln p - gamma ln rho, for
+ * total energy including rho*phi:
+ * v = ((gamma - s)/(gamma-1) - b|u|^2 + 2 b phi, 2 b u, -2 b), b = rho/(2p). */
+void oracle_entropy_vars(const double q[5], double phi, double gamma, double v[5])
+{
+    double rho = q[0];
+    double p = pressure(q, phi, gamma);
+    double b = rho / (2.0 * p);
+    double u[3] = {q[1] / rho, q[2] / rho, q[3] / rho};
+    double s = log(p) - gamma * log(rho);
+    v[0] = (gamma - s) / (gamma - 1.0) - b * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) +
+           2.0 * b * phi;
+    v[1] = 2.0 * b * u[0];
+    v[2] = 2.0 * b * u[1];
+    v[3] = 2.0 * b * u[2];
+    v[4] = -2.0 * b;
+}
+
+double oracle_entropy_density(const double q[5], double phi, double gamma)
+{
+    double p = pressure(q, phi, gamma);
+    double s = log(p) - gamma * log(q[0]);
+    return -q[0] * s / (gamma - 1.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Right-hand side                                                           */
+/* ------------------------------------------------------------------------ */
+
+static inline void load_node(const double *q, int64_t e, int Np, int n, double out[5])
+{
+    for (int v = 0; v < 5; ++v) out[v] = q[(e * 5 + v) * Np + n];
+}
+
+/* Neighbour across the face of element (ex,ey,ez) in direction r, side s.
+ * Returns the neighbour element index, or -1 at a reflecting wall. */
+static int64_t neighbour(const omesh *m, const int ee[3], int r, int s)
+{
+    int nb[3] = {ee[0], ee[1], ee[2]};
+    nb[r] += s;
+    if (nb[r] < 0 || nb[r] >= m->K[r]) {
+        if (!m->periodic[r]) return -1;
+        nb[r] = (nb[r] + m->K[r]) % m->K[r];
+    }
+    return elem_index(m, nb[0], nb[1], nb[2]);
+}
+
+/* Plus-side state at face node n of element e (own node index ii[]) in
+ * direction r, side s: the neighbour's coincident node, or the mirror state
+ * (rho, m - 2 (m.n) n, E) with phi+ = phi- at a wall. */
+static void plus_state(const omesh *m, const double *q, int64_t e, const int ee[3],
+                       const int ii[3], int r, int s, double qp[5], double *phip)
+{
+    int64_t en = neighbour(m, ee, r, s);
+    const int Nq = m->Nq, Np = m->Np;
+    int n = ii[0] + Nq * (ii[1] + Nq * ii[2]);
+    if (en < 0) {
+        load_node(q, e, Np, n, qp);
+        qp[1 + r] = -qp[1 + r];
+        *phip = m->phi[e * Np + n];
+        return;
+    }
+    int jj[3] = {ii[0], ii[1], ii[2]};
+    jj[r] = (s < 0) ? m->N : 0;
+    int nn = jj[0] + Nq * (jj[1] + Nq * jj[2]);
+    load_node(q, en, Np, nn, qp);
+    *phip = m->phi[en * Np + nn];
+}
+
+/* R for one element in the skew (flux-differencing) form that the printed
+ * semi-discrete equation (nm:semi) stands for on affine hexahedra:
+ *   R_a = h_a - sum_r (2/h_r)(1/w_{i_r(a)}) sum_{b on the r-line of a}
+ *                   S_{i_r(a) i_r(b)} F_r(a, b)
+ *         - sum over faces of a: (2/h_r)(1/w_0) F*.n
+ * with S = W D - (W D)^T.  Every ordered pair (a, b) is evaluated; nothing
+ * uses the flux symmetry.  `gross` (if not NULL) receives the sum of the
+ * absolute values of all terms, used as the scale of roundoff. */
+static void rhs_element(const omesh *m, const double *q, double *R, double *gross,
+                        int64_t e, int mask)
+{
+    const int N = m->N, Nq = m->Nq, Np = m->Np;
+    int ee[3];
+    ee[0] = (int)(e % m->K[0]);
+    ee[1] = (int)((e / m->K[0]) % m->K[1]);
+    ee[2] = (int)(e / ((int64_t)m->K[0] * m->K[1]));
+    for (int k = 0; k < Nq; ++k)
+        for (int j = 0; j < Nq; ++j)
+            for (int i = 0; i < Nq; ++i) {
+                int ii[3] = {i, j, k};
+                int a = i + Nq * (j + Nq * k);
+                double qa[5], acc[5] = {0, 0, 0, 0, 0}, gacc[5] = {0, 0, 0, 0, 0};
+                load_node(q, e, Np, a, qa);
+                double phia = m->phi[e * Np + a];
+                if (mask & TERM_VOL) {
+                    for (int r = 0; r < 3; ++r) {
+                        int ia = ii[r];
+                        for (int l = 0; l < Nq; ++l) {
+                            if (l == ia) continue;
+                            int jj[3] = {i, j, k};
+                            jj[r] = l;
+                            int b = jj[0] + Nq * (jj[1] + Nq * jj[2]);
+                            double qb[5], F[5];
+                            load_node(q, e, Np, b, qb);
+                            oracle_two_point_flux(r, qa, qb, phia, m->phi[e * Np + b], m->gamma, F);
+                            double coef = -(2.0 / m->h[r]) * m->S[ia][l] / m->w[ia];
+                            for (int v = 0; v < 5; ++v) {
+                                acc[v] += coef * F[v];
+                                gacc[v] += fabs(coef * F[v]);
+                            }
+                        }
+                    }
+                }
+                if (mask & TERM_FACE) {
+                    for (int r = 0; r < 3; ++r) {
+                        int sides[2] = {0, 0}, ns = 0;
+                        if (ii[r] == 0) sides[ns++] = -1;
+                        if (ii[r] == N) sides[ns++] = +1;
+                        for (int t = 0; t < ns; ++t) {
+                            int s = sides[t];
+                            double qp[5], phip, Fn[5];
+                            plus_state(m, q, e, ee, ii, r, s, qp, &phip);
+                            oracle_surface_flux(r, s, qa, qp, phia, phip, m->gamma, m->surf, Fn);
+                            double coef = -(2.0 / m->h[r]) / m->w[ii[r]];
+                            for (int v = 0; v < 5; ++v) {
+                                acc[v] += coef * Fn[v];
+                                gacc[v] += fabs(coef * Fn[v]);
+                            }
+                        }
+                    }
+                }
+                if (mask & TERM_SRC) {
+                    /* -Omega x U with Omega = f z_hat */
+                    acc[1] += m->cor_f * qa[2];
+                    acc[2] -= m->cor_f * qa[1];
+                    gacc[1] += fabs(m->cor_f * qa[2]);
+                    gacc[2] += fabs(m->cor_f * qa[1]);
+                }
+                for (int v = 0; v < 5; ++v) {
+                    R[(e * 5 + v) * Np + a] = acc[v];
+                    if (gross) gross[(e * 5 + v) * Np + a] = gacc[v];
+                }
+            }
+}
+
+int oracle_rhs_terms(void *mp, const double *q, double *R, double *gross, int mask)
+{
+    omesh *m = (omesh *)mp;
+    int64_t e;
+#pragma omp parallel for schedule(static)
+    for (e = 0; e < m->ne; ++e) rhs_element(m, q, R, gross, e, mask);
+    return 0;
+}
+
+int oracle_rhs(void *mp, const double *q, double *R)
+{
+    return oracle_rhs_terms(mp, q, R, NULL, TERM_VOL | TERM_FACE | TERM_SRC);
+}
+
+/* R (and gross) only for the listed elements; other entries untouched. */
+int oracle_rhs_elems(void *mp, const double *q, double *R, double *gross, int mask,
+                     const int64_t *elems, int64_t nelems)
+{
+    omesh *m = (omesh *)mp;
+    int64_t t;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (t = 0; t < nelems; ++t) rhs_element(m, q, R, gross, elems[t], mask);
+    return 0;
+}
+
+/* Brute-force strong form, written independently of the skew form:
+ *   R_a = h_a - sum_r (2/h_r) [ sum_l 2 D_{i l} F_r(a, b_l)              (l = i included)
+ *                              + (F*.n - s f_r(q_a)) / w_{i}  at faces ]
+ * where f_r is the physical Euler flux.  Exactly equal to the skew form in
+ * exact arithmetic (summation by parts); used to pin it on tiny meshes. */
+int oracle_rhs_strong(void *mp, const double *q, double *R)
+{
+    omesh *m = (omesh *)mp;
+    const int N = m->N, Nq = m->Nq, Np = m->Np;
+    for (int64_t e = 0; e < m->ne; ++e) {
+        int ee[3];
+        ee[0] = (int)(e % m->K[0]);
+        ee[1] = (int)((e / m->K[0]) % m->K[1]);
+        ee[2] = (int)(e / ((int64_t)m->K[0] * m->K[1]));
+        for (int a = 0; a < Np; ++a) {
+            int ii[3] = {a % Nq, (a / Nq) % Nq, a / (Nq * Nq)};
+            double qa[5], acc[5] = {0, 0, 0, 0, 0};
+            load_node(q, e, Np, a, qa);
+            double phia = m->phi[e * Np + a];
+            for (int r = 0; r < 3; ++r) {
+                double sum[5] = {0, 0, 0, 0, 0};
+                for (int l = 0; l < Nq; ++l) {
+                    int jj[3] = {ii[0], ii[1], ii[2]};
+                    jj[r] = l;
+                    int b = jj[0] + Nq * (jj[1] + Nq * jj[2]);
+                    double qb[5], F[5];
+                    load_node(q, e, Np, b, qb);
+                    oracle_two_point_flux(r, qa, qb, phia, m->phi[e * Np + b], m->gamma, F);
+                    for (int v = 0; v < 5; ++v) sum[v] += 2.0 * m->D[ii[r]][l] * F[v];
+                }
+                for (int s = -1; s <= 1; s += 2) {
+                    if ((s < 0 && ii[r] != 0) || (s > 0 && ii[r] != N)) continue;
+                    double qp[5], phip, Fn[5], f[5];
+                    plus_state(m, q, e, ee, ii, r, s, qp, &phip);
+                    oracle_surface_flux(r, s, qa, qp, phia, phip, m->gamma, m->surf, Fn);
+                    oracle_euler_flux(r, qa, phia, m->gamma, f);
+                    for (int v = 0; v < 5; ++v) sum[v] += (Fn[v] - s * f[v]) / m->w[ii[r]];
+                }
+                for (int v = 0; v < 5; ++v) acc[v] -= (2.0 / m->h[r]) * sum[v];
+            }
+            acc[1] += m->cor_f * qa[2];
+            acc[2] -= m->cor_f * qa[1];
+            for (int v = 0; v < 5; ++v) R[(e * 5 + v) * Np + a] = acc[v];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* LSRK(5,4), 2N-storage (Carpenter & Kennedy 1994)                          */
+/* ------------------------------------------------------------------------ */
+
+static const double LSRK_A[5] = {
+    0.0,
+    -567301805773.0 / 1357537059087.0,
+    -2404267990393.0 / 2016746695238.0,
+    -3550918686646.0 / 2091501179385.0,
+    -1275806237668.0 / 842570457699.0,
+};
+static const double LSRK_B[5] = {
+    1432997174477.0 / 9575080441755.0,
+    5161836677717.0 / 13612068292357.0,
+    1720146321549.0 / 2090206949498.0,
+    3134564353537.0 / 4481467310338.0,
+    2277821191437.0 / 14882151754819.0,
+};
+static const double LSRK_C[5] = {
+    0.0,
+    1432997174477.0 / 9575080441755.0,
+    2526269341429.0 / 6820363962896.0,
+    2006345519317.0 / 3224310063776.0,
+    2802321613138.0 / 2924317926251.0,
+};
+
+void oracle_lsrk_coeffs(double *A, double *B, double *C)
+{
+    for (int s = 0; s < 5; ++s) {
+        A[s] = LSRK_A[s];
+        B[s] = LSRK_B[s];
+        C[s] = LSRK_C[s];
+    }
+}
+
+typedef void (*rhs_fn)(void *ctx, const double *q, double *r, double t);
+
+/* One 2N-storage step: for s = 1..5,
+ *   dq <- A_s dq + dt R(q, t + C_s dt);  q <- q + B_s dq. */
+static void lsrk_advance(int64_t n, double *q, double *dq, double *R, double t, double dt,
+                         rhs_fn f, void *ctx)
+{
+    for (int s = 0; s < 5; ++s) {
+        f(ctx, q, R, t + LSRK_C[s] * dt);
+        for (int64_t i = 0; i < n; ++i) {
+            dq[i] = LSRK_A[s] * dq[i] + dt * R[i];
+            q[i] = q[i] + LSRK_B[s] * dq[i];
+        }
+    }
+}
+
+static void mesh_rhs_cb(void *ctx, const double *q, double *r, double t)
+{
+    (void)t;
+    oracle_rhs(ctx, q, r);
+}
+
+/* One LSRK(5,4) step of the mesh ODE dq/dt = R(q), in place.  dq is the
+ * caller's second register (its contents on entry are irrelevant: A_1 = 0). */
+int oracle_lsrk_step(void *mp, double *q, double *dq, double t, double dt)
+{
+    omesh *m = (omesh *)mp;
+    int64_t n = m->nn * 5;
+    double *R = (double *)malloc(sizeof(double) * n);
+    if (!R) return -1;
+    lsrk_advance(n, q, dq, R, t, dt, mesh_rhs_cb, m);
+    free(R);
+    return 0;
+}
+
+typedef struct {
+    int n;
+    const double *M;
+} lin_ctx;
+
+static void lin_rhs_cb(void *ctx, const double *q, double *r, double t)
+{
+    (void)t;
+    const lin_ctx *c = (const lin_ctx *)ctx;
+    for (int i = 0; i < c->n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < c->n; ++j) s += c->M[i * c->n + j] * q[j];
+        r[i] = s;
+    }
+}
+
+typedef struct {
+    int m;
+} poly_ctx;
+
+static void poly_rhs_cb(void *ctx, const double *q, double *r, double t)
+{
+    (void)q;
+    const poly_ctx *c = (const poly_ctx *)ctx;
+    r[0] = (c->m == 0) ? 1.0 : (double)c->m * pow(t, c->m - 1);
+}
+
+/* The same stepping routine applied to the linear ODE y' = M y (n <= 16),
+ * used to read off the stability polynomial. */
+int oracle_lsrk_linear(int n, const double *M, double *y, double dt, int nsteps)
+{
+    double dq[16] = {0}, R[16];
+    if (n > 16) return -1;
+    lin_ctx c = {n, M};
+    for (int s = 0; s < nsteps; ++s) lsrk_advance(n, y, dq, R, 0.0, dt, lin_rhs_cb, &c);
+    return 0;
+}
+
+/* The same stepping routine applied to y' = m t^(m-1), y(t0) = y0. */
+double oracle_lsrk_poly(int mpow, double t0, double y0, double dt, int nsteps)
+{
+    double y = y0, dq = 0.0, R;
+    poly_ctx c = {mpow};
+    double t = t0;
+    for (int s = 0; s < nsteps; ++s) {
+        lsrk_advance(1, &y, &dq, &R, t, dt, poly_rhs_cb, &c);
+        t += dt;
+    }
+    return y;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* out[0] = sum_K int eta, out[1] = sum_K int rho, out[2] = sum_K int E,
+ * out[3] = sum_a J w_a v_a . R_a(q) (the discrete entropy production),
+ * all with the LGL quadrature and J = h_x h_y h_z / 8. */
+int oracle_entropy(void *mp, const double *q, double *out)
+{
+    omesh *m = (omesh *)mp;
+    const int Nq = m->Nq, Np = m->Np;
+    double J = m->h[0] * m->h[1] * m->h[2] / 8.0;
+    double *R = (double *)malloc(sizeof(double) * m->nn * 5);
+    if (!R) return -1;
+    oracle_rhs(mp, q, R);
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int64_t e = 0; e < m->ne; ++e)
+        for (int a = 0; a < Np; ++a) {
+            int i = a % Nq, j = (a / Nq) % Nq, k = a / (Nq * Nq);
+            double wq = J * m->w[i] * m->w[j] * m->w[k];
+            double qa[5], v[5];
+            load_node(q, e, Np, a, qa);
+            double phi = m->phi[e * Np + a];
+            oracle_entropy_vars(qa, phi, m->gamma, v);
+            double vr = 0.0;
+            for (int c = 0; c < 5; ++c) vr += v[c] * R[(e * 5 + c) * Np + a];
+            s0 += wq * oracle_entropy_density(qa, phi, m->gamma);
+            s1 += wq * qa[0];
+            s2 += wq * qa[4];
+            s3 += wq * vr;
+        }
+    free(R);
+    out[0] = s0;
+    out[1] = s1;
+    out[2] = s2;
+    out[3] = s3;
+    return 0;
+}
+
+/* dt = CFL / ((N+1) max_a sum_r (|u_r| + c)/h_r). */
+double oracle_cfl_dt(void *mp, const double *q, double cfl)
+{
+    omesh *m = (omesh *)mp;
+    const int Np = m->Np;
+    double smax = 0.0;
+    for (int64_t e = 0; e < m->ne; ++e)
+        for (int a = 0; a < Np; ++a) {
+            double qa[5];
+            load_node(q, e, Np, a, qa);
+            double p = pressure(qa, m->phi[e * Np + a], m->gamma);
+            double c = sqrt(m->gamma * p / qa[0]);
+            double s = 0.0;
+            for (int r = 0; r < 3; ++r) s += (fabs(qa[1 + r] / qa[0]) + c) / m->h[r];
+            if (s > smax) smax = s;
+        }
+    return cfl / ((m->N + 1) * smax);
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

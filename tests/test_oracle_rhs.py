@@ -1,0 +1,232 @@
+"""Mesh-level pins of the oracle's R(q) and LSRK step.
+
+Paper: semi-discrete ES-DGSEM (Sec. 3, Eq. nm:semi, read as the
+Jacobian-weighted skew flux-differencing form), discrete entropy stability
+of the two-point flux (Sec. 3), conservation of mass and total energy to
+machine precision (Sec. 6.2), LSRK(5,4) stepping (Sec. 3).  Every check is
+against mathematics that does not come from the oracle itself: the strong
+form written independently, exact solutions, invariants, and the entropy
+variables as the gradient of eta.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_16684_amd import workloads as W
+
+G = 1.4
+
+
+def _quad_weights(m):
+    xi, w, _, _ = m.tables()
+    Nq = m.Nq
+    wq = (w[None, None, :] * w[None, :, None] * w[:, None, None]).reshape(-1)  # n = i + Nq(j + Nq k)
+    J = m.h[0] * m.h[1] * m.h[2] / 8.0
+    return J * wq
+
+
+def _entropy_vars_field(q, phi):
+    p = (G - 1) * (q[:, 4] - 0.5 * (q[:, 1] ** 2 + q[:, 2] ** 2 + q[:, 3] ** 2) / q[:, 0]
+                   - q[:, 0] * phi)
+    rho = q[:, 0]
+    b = rho / (2 * p)
+    s = np.log(p) - G * np.log(rho)
+    u2 = (q[:, 1] ** 2 + q[:, 2] ** 2 + q[:, 3] ** 2) / rho ** 2
+    v = np.empty_like(q)
+    v[:, 0] = (G - s) / (G - 1) - b * u2 + 2 * b * phi
+    v[:, 1:4] = 2 * b[:, None] * q[:, 1:4] / rho[:, None]
+    v[:, 4] = -2 * b
+    return v
+
+
+def _mesh(spec, **kw):
+    d = dict(gamma=spec.gamma, gas_R=spec.gas_R, grav=spec.grav, coriolis_f=spec.coriolis_f,
+             surface_flux=spec.surface_flux)
+    d.update(kw)
+    return O.Mesh(spec.N, spec.K, spec.lo, spec.hi, spec.periodic, **d)
+
+
+def _rel_gross(a, b, g):
+    return np.sqrt(((a - b) ** 2).sum(axis=(0, 2))) / np.maximum(np.sqrt((g ** 2).sum(axis=(0, 2))),
+                                                                 1e-300)
+
+
+@pytest.mark.parametrize("N,K,periodic,f", [
+    (3, (1, 1, 1), (1, 1, 0), 0.0),
+    (4, (2, 1, 1), (0, 1, 0), 1e-4),
+    (2, (1, 2, 1), (1, 0, 0), 1e-4),
+    (5, (1, 1, 2), (1, 1, 0), 0.0),
+])
+def test_skew_form_equals_strong_form(N, K, periodic, f):
+    spec = W.MeshSpec(N, K, (0, 0, 0), (700.0, 900.0, 1100.0), periodic, coriolis_f=f)
+    m = _mesh(spec)
+    q = W.state_iso_pert(m.coords(), spec, seed=7, amp_rho=1e-2, amp_u=5.0)
+    r, g = m.rhs(q, gross=True)
+    rs = m.rhs_strong(q)
+    assert np.all(_rel_gross(r, rs, g) < 1e-14)
+
+
+def test_free_stream_preservation():
+    spec = W.MeshSpec(4, (3, 2, 2), (0, 0, 0), (1.0, 2.0, 3.0), (1, 1, 1), grav=0.0)
+    m = _mesh(spec)
+    q = W.constant_state(m.ne, m.Np)
+    r, g = m.rhs(q, gross=True)
+    assert np.all(_rel_gross(r, 0 * r, g) < 1e-15)
+
+
+@pytest.mark.parametrize("N", [3, 4, 7])
+def test_isothermal_hydrostatic_well_balanced(N):
+    spec = W.MeshSpec(N, (2, 2, 4), (0, 0, 0), (2000.0, 2000.0, 30000.0), (1, 1, 0))
+    m = _mesh(spec)
+    q = W.state_iso_rest(m.coords(), spec, T=250.0)
+    r, g = m.rhs(q, gross=True)
+    assert np.all(_rel_gross(r, 0 * r, g) < 1e-15)
+    # the momentum residual is pure roundoff: far below the hydrostatic terms
+    assert np.abs(r[:, 3]).max() < 1e-9
+
+
+@pytest.mark.parametrize("periodic", [(1, 1, 0), (0, 0, 0), (1, 0, 0)])
+def test_conservation_of_mass_and_energy(periodic):
+    spec = W.MeshSpec(3, (3, 2, 3), (0, 0, 0), (1000.0, 1000.0, 1000.0), periodic,
+                      coriolis_f=1e-4)
+    m = _mesh(spec)
+    q = W.state_iso_pert(m.coords(), spec, seed=11, amp_rho=1e-2, amp_u=10.0)
+    r, g = m.rhs(q, gross=True)
+    wq = _quad_weights(m)
+    for v in (0, 4):
+        total = (wq[None, :] * r[:, v]).sum()
+        scale = (wq[None, :] * g[:, v]).sum()
+        assert abs(total) <= 1e-15 * scale, (v, total, scale)
+
+
+def test_entropy_conservation_periodic_no_gravity():
+    spec = W.MeshSpec(3, (2, 3, 2), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 1), grav=0.0,
+                      surface_flux=O.SURF_EC)
+    m = _mesh(spec)
+    q = W.state_iso_pert(m.coords(), spec, seed=3, amp_rho=5e-2, amp_u=20.0)
+    r, g = m.rhs(q, gross=True)
+    v = _entropy_vars_field(q, m.phi())
+    wq = _quad_weights(m)
+    prod = (wq[None, None, :] * v * r).sum()
+    scale = (wq[None, None, :] * np.abs(v) * g).sum()
+    assert abs(prod) <= 1e-14 * scale, (prod, scale)
+    assert abs(m.entropy(q)[3] - prod) <= 1e-12 * scale
+
+
+def test_entropy_conservation_periodic_with_gravity_term():
+    # phi periodic in z so that the box can be periodic in every direction;
+    # the gravity two-point term must keep the volume terms entropy conservative
+    spec = W.MeshSpec(4, (2, 2, 3), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 1),
+                      surface_flux=O.SURF_EC)
+    m = _mesh(spec)
+    xyz = m.coords()
+    phi = 9.81 * 150.0 * np.sin(2 * math.pi * xyz[:, 2] / 1000.0)
+    m.set_phi(phi)
+    rng = np.random.default_rng(5)
+    rho = 1.0 + 0.1 * np.cos(2 * math.pi * xyz[:, 0] / 1000.0 + rng.uniform())
+    u = 3.0 * np.sin(2 * math.pi * (xyz[:, 1] + xyz[:, 2]) / 1000.0)
+    p = 1e5 * (1 + 0.05 * np.cos(2 * math.pi * xyz[:, 2] / 1000.0))
+    q = np.stack([rho, rho * u, 0 * rho, rho * u, p / (G - 1) + rho * u * u + rho * phi], axis=1)
+    r, g = m.rhs(q, gross=True)
+    v = _entropy_vars_field(q, phi)
+    wq = _quad_weights(m)
+    prod = (wq[None, None, :] * v * r).sum()
+    scale = (wq[None, None, :] * np.abs(v) * g).sum()
+    assert abs(prod) <= 1e-14 * scale, (prod, scale)
+    # with jumps at the faces, Rusanov faces dissipate entropy
+    q[:, 0] *= 1.0 + 0.01 * rng.uniform(-1, 1, q[:, 0].shape)
+    q[:, 4] += q[:, 0] * 0  # keep E: the pressure changes with rho*phi
+    v = _entropy_vars_field(q, phi)
+    m2 = O.Mesh(4, spec.K, spec.lo, spec.hi, spec.periodic, surface_flux=O.SURF_RUSANOV)
+    m2.set_phi(phi)
+    r2, g2 = m2.rhs(q, gross=True)
+    scale2 = (wq[None, None, :] * np.abs(v) * g2).sum()
+    assert (wq[None, None, :] * v * r2).sum() < -1e-6 * scale2
+
+
+def test_entropy_conservation_walls_with_gravity():
+    spec = W.MeshSpec(3, (2, 2, 3), (0, 0, 0), (1000.0, 1000.0, 3000.0), (0, 1, 0),
+                      surface_flux=O.SURF_EC, coriolis_f=1e-4)
+    m = _mesh(spec)
+    q = W.state_iso_pert(m.coords(), spec, seed=8, amp_rho=1e-2, amp_u=5.0)
+    r, g = m.rhs(q, gross=True)
+    v = _entropy_vars_field(q, m.phi())
+    wq = _quad_weights(m)
+    prod = (wq[None, None, :] * v * r).sum()
+    scale = (wq[None, None, :] * np.abs(v) * g).sum()
+    assert abs(prod) <= 1e-14 * scale, (prod, scale)
+
+
+def test_entropy_dissipation_rusanov():
+    spec = W.iso_pert_cube().mesh
+    m = _mesh(spec)
+    q = W.state_iso_pert(m.coords(), spec, seed=1)
+    assert m.entropy(q)[3] < 0.0
+
+
+def test_coriolis_source_is_entropy_neutral():
+    spec = W.MeshSpec(3, (2, 2, 2), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 0),
+                      coriolis_f=1e-4)
+    m = _mesh(spec)
+    q = W.state_iso_pert(m.coords(), spec, seed=2, amp_u=10.0)
+    r = m.rhs(q, mask=O.TERM_SRC)
+    assert np.array_equal(r[:, 1], 1e-4 * q[:, 2]) and np.array_equal(r[:, 2], -1e-4 * q[:, 1])
+    assert np.all(r[:, [0, 3, 4]] == 0)
+    v = _entropy_vars_field(q, m.phi())
+    assert np.abs((v * r).sum(axis=1)).max() <= 1e-15 * np.abs(v * r).max()
+
+
+def test_term_split_sums_to_full_rhs():
+    spec = W.iso_pert_cube().mesh
+    m = _mesh(spec, coriolis_f=1e-4)
+    q = W.state_iso_pert(m.coords(), spec, seed=4)
+    full, g = m.rhs(q, gross=True)
+    parts = sum(m.rhs(q, mask=t) for t in (O.TERM_VOL, O.TERM_FACE, O.TERM_SRC))
+    assert np.all(_rel_gross(full, parts, g) < 1e-16)
+
+
+def test_density_wave_convergence():
+    # exact Euler solution without gravity; L2 error at t = T must fall at
+    # order >= N under refinement
+    N, T = 3, 0.05
+    errs = []
+    for K in (2, 4, 8):
+        spec = W.MeshSpec(N, (K, K, K), (0, 0, 0), (1.0, 1.0, 1.0), (1, 1, 1), grav=0.0)
+        m = _mesh(spec)
+        xyz = m.coords()
+        q0 = W.density_wave(xyz, spec)
+        nsteps = 8 * K
+        q = m.run(q0, T / nsteps, nsteps)
+        ex = W.density_wave(xyz, spec, t=T)
+        wq = _quad_weights(m)
+        errs.append(math.sqrt((wq[None, :] * (q[:, 0] - ex[:, 0]) ** 2).sum()))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(rates) >= N, (errs, rates)
+
+
+def test_lsrk_run_conserves_mass_and_energy_100_steps():
+    wl = W.iso_pert_cube()
+    m = _mesh(wl.mesh)
+    q0 = W.state_iso_pert(m.coords(), wl.mesh, seed=1)
+    dt = m.cfl_dt(q0, wl.cfl)
+    e0 = m.entropy(q0)
+    q = m.run(q0, dt, 100)
+    e1 = m.entropy(q)
+    assert abs(e1[1] - e0[1]) <= 2e-14 * abs(e0[1])
+    assert abs(e1[2] - e0[2]) <= 2e-14 * abs(e0[2])
+    assert e1[0] <= e0[0]           # mathematical entropy decreases with Rusanov faces
+    assert np.all(np.isfinite(q))
+
+
+def test_cfl_dt_formula():
+    wl = W.iso_pert_cube()
+    m = _mesh(wl.mesh)
+    q = W.state_iso_pert(m.coords(), wl.mesh, seed=1)
+    rho = q[:, 0]
+    u = q[:, 1:4] / rho[:, None]
+    p = (G - 1) * (q[:, 4] - 0.5 * rho * (u ** 2).sum(axis=1) - rho * m.phi())
+    c = np.sqrt(G * p / rho)
+    s = sum((np.abs(u[:, r]) + c) / m.h[r] for r in range(3))
+    assert abs(m.cfl_dt(q, 0.5) - 0.5 / ((m.N + 1) * s.max())) < 1e-15
