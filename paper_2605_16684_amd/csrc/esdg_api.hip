@@ -1,0 +1,634 @@
+// esdg_api.hip -- C ABI of the gfx950 ES-DGSEM library (see include/esdg.h).
+//
+// Host side: argument validation, per-device LGL tables, the mesh object
+// (tables, scratch, captured graphs) and kernel launches.  All arithmetic of
+// the method runs in the kernels of esdg_device.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "esdg.h"
+#include "esdg_device.hpp"
+
+using namespace esdg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            return fail(ESDG_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e));           \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// LGL tables (host).  Interior nodes are the roots of the Jacobi polynomial
+// P^(1,1)_{N-1} (proportional to P_N'), found by Newton's method on its
+// three-term recurrence in extended precision; weights 2/(N(N+1) P_N^2);
+// the derivative matrix from barycentric weights with the negative-sum
+// diagonal.
+// ---------------------------------------------------------------------------
+
+void jacobi11(int n, long double x, long double *p, long double *dp)
+{
+    long double pm2 = 1.0L, dpm2 = 0.0L;
+    if (n == 0) { *p = 1.0L; *dp = 0.0L; return; }
+    long double pm1 = 2.0L * x, dpm1 = 2.0L;
+    for (int k = 2; k <= n; ++k) {
+        const long double a = 4.0L * k * k * (k + 2.0L);
+        const long double b = (2.0L * k + 1.0L) * (2.0L * k + 2.0L) * (2.0L * k);
+        const long double c = 2.0L * k * k * (2.0L * k + 2.0L);
+        const long double pk = (b * x * pm1 - c * pm2) / a;
+        const long double dpk = (b * (x * dpm1 + pm1) - c * dpm2) / a;
+        pm2 = pm1; dpm2 = dpm1;
+        pm1 = pk; dpm1 = dpk;
+    }
+    *p = pm1;
+    *dp = dpm1;
+}
+
+long double legendre(int n, long double x)
+{
+    long double a = 1.0L, b = x;
+    if (n == 0) return 1.0L;
+    for (int k = 2; k <= n; ++k) {
+        const long double c = ((2.0L * k - 1.0L) * x * b - (k - 1.0L) * a) / k;
+        a = b;
+        b = c;
+    }
+    return b;
+}
+
+void lgl_tables(int N, double *xi_out, double *w_out, double *D_out)
+{
+    const int Nq = N + 1;
+    long double x[NQ_MAX];
+    x[0] = -1.0L;
+    x[N] = 1.0L;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 1; i < N; ++i) {
+        long double t = -std::cos(pi * (long double)i / (long double)N);
+        for (int it = 0; it < 200; ++it) {
+            long double p, dp;
+            jacobi11(N - 1, t, &p, &dp);
+            const long double step = p / dp;
+            t -= step;
+            if (std::fabs(step) <= 1e-21L) break;
+        }
+        x[i] = t;
+    }
+    for (int i = 0; i < Nq / 2; ++i) {  // exact mirror symmetry
+        const long double s = 0.5L * (x[N - i] - x[i]);
+        x[i] = -s;
+        x[N - i] = s;
+    }
+    if (N % 2 == 0) x[N / 2] = 0.0L;
+    long double lam[NQ_MAX];
+    for (int j = 0; j < Nq; ++j) {
+        long double prod = 1.0L;
+        for (int k = 0; k < Nq; ++k)
+            if (k != j) prod *= (x[j] - x[k]);
+        lam[j] = 1.0L / prod;
+    }
+    for (int i = 0; i < Nq; ++i) {
+        const long double pn = legendre(N, x[i]);
+        xi_out[i] = (double)x[i];
+        w_out[i] = (double)(2.0L / ((long double)N * (N + 1.0L) * pn * pn));
+        long double diag = 0.0L;
+        for (int j = 0; j < Nq; ++j) {
+            if (j == i) continue;
+            const long double d = (lam[j] / lam[i]) / (x[i] - x[j]);
+            D_out[i * Nq + j] = (double)d;
+            diag -= d;
+        }
+        D_out[i * Nq + i] = (double)diag;
+    }
+}
+
+OrderTables make_order_tables(int N)
+{
+    OrderTables t;
+    std::memset(&t, 0, sizeof t);
+    const int Nq = N + 1;
+    double D[NQ_MAX * NQ_MAX];
+    lgl_tables(N, t.xi, t.w, D);
+    for (int i = 0; i < Nq; ++i) t.winv[i] = 1.0 / t.w[i];
+    for (int a = 0; a < Nq; ++a)
+        for (int b = 0; b < Nq; ++b)
+            t.T[a][b] = (a == b) ? 0.0 : D[a * Nq + b] - (t.w[b] / t.w[a]) * D[b * Nq + a];
+    return t;
+}
+
+std::mutex g_init_mu;
+bool g_dev_init[64];
+
+int ensure_tables(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (dev < 0 || dev >= 64) return fail(ESDG_EINVAL, "device id %d out of range", dev);
+    if (g_dev_init[dev]) return ESDG_OK;
+    OrderTables tabs[NQ_MAX];
+    for (int N = 1; N <= NQ_MAX - 1; ++N) tabs[N - 1] = make_order_tables(N);
+    std::memset(&tabs[NQ_MAX - 1], 0, sizeof(OrderTables));
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_tab), tabs, sizeof tabs, 0, hipMemcpyHostToDevice));
+    g_dev_init[dev] = true;
+    return ESDG_OK;
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Mesh object
+// ---------------------------------------------------------------------------
+
+struct esdg_mesh {
+    esdg_mesh_desc desc;
+    int device;
+    hipStream_t stream;
+    int N, Nq, Np;
+    int64_t ne, nn, state_len;
+    int epw;
+    double h[3];
+    double *d_q2;        // ping-pong state
+    double *d_r;         // RHS scratch (entropy production)
+    double *d_partials;  // reduction partials
+    double *d_red_out;   // 4 doubles
+    int *d_flag;
+    double *h_out;       // pinned, 4 doubles
+    int *h_flag;         // pinned
+    int64_t red_blocks;
+    int64_t footprint;
+    // captured two-step graph for esdg_lsrk_run
+    hipGraphExec_t graph_exec;
+    const double *g_q;
+    const double *g_dq;
+    double g_dt;
+    hipStream_t g_stream;
+    int g_epw;
+};
+
+namespace {
+
+// Compiled (N, EPW) variants of the fused stage kernel.
+typedef void (*stage_kernel_t)(StageParams);
+
+struct Variant {
+    int N, epw, threads;
+    stage_kernel_t fn;
+};
+
+#define V(NN, E) {NN, E, block_threads<NN + 1, E>(), stage_fp64<NN + 1, E>}
+const Variant kVariants[] = {
+    V(1, 8), V(1, 16), V(1, 32),
+    V(2, 4), V(2, 7), V(2, 14),
+    V(3, 2), V(3, 4), V(3, 8),
+    V(4, 1), V(4, 2), V(4, 5),
+    V(5, 1), V(5, 3),
+    V(6, 1), V(6, 2),
+    V(7, 1), V(7, 2),
+    V(8, 1),
+};
+#undef V
+
+const Variant *find_variant(int N, int epw)
+{
+    for (const Variant &v : kVariants)
+        if (v.N == N && v.epw == epw) return &v;
+    return nullptr;
+}
+
+int default_epw(int N)
+{
+    switch (N) {
+    case 1: return 16;
+    case 2: return 7;
+    case 3: return 4;
+    case 4: return 5;
+    case 5: return 3;
+    case 6: return 2;
+    case 7: return 1;
+    default: return 1;
+    }
+}
+
+GeomParams geom(const esdg_mesh *m)
+{
+    GeomParams G;
+    G.ne = m->ne;
+    G.N = m->N;
+    for (int d = 0; d < 3; ++d) {
+        G.K[d] = m->desc.K[d];
+        G.lo[d] = m->desc.lo[d];
+        G.hi[d] = m->desc.hi[d];
+        G.h[d] = m->h[d];
+    }
+    G.gamma = m->desc.gamma;
+    G.grav = m->desc.grav;
+    G.lnz_scale = m->desc.gas_R * 300.0;
+    return G;
+}
+
+StageParams base_params(const esdg_mesh *m)
+{
+    StageParams P;
+    std::memset(&P, 0, sizeof P);
+    P.ne = m->ne;
+    for (int d = 0; d < 3; ++d) {
+        P.K[d] = m->desc.K[d];
+        P.periodic[d] = m->desc.periodic[d] ? 1 : 0;
+        P.two_h[d] = 2.0 / m->h[d];
+    }
+    P.zlo = m->desc.lo[2];
+    P.zhi = m->desc.hi[2];
+    P.gamma = m->desc.gamma;
+    P.grav = m->desc.grav;
+    P.cor_f = m->desc.coriolis_f;
+    P.lnz_scale = m->desc.gas_R * 300.0;
+    P.surf = m->desc.surface_flux;
+    P.flag = m->d_flag;
+    P.mask = TERM_VOL | TERM_FACE | TERM_SRC;
+    return P;
+}
+
+int launch_stage(esdg_mesh *m, StageParams P)
+{
+    const Variant *v = find_variant(m->N, m->epw);
+    if (!v) return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", m->N, m->epw);
+    const int64_t nb = (m->ne + m->epw - 1) / m->epw;
+    if (nb > 0x7fffffff) return fail(ESDG_EINVAL, "mesh too large");
+    P.nblocks = (int)nb;
+    hipLaunchKernelGGL(v->fn, dim3((unsigned)nb), dim3(v->threads), 0, m->stream, P);
+    HIP_TRY(hipGetLastError());
+    return ESDG_OK;
+}
+
+// LSRK(5,4) coefficients of Carpenter and Kennedy (published rationals).
+const double kA[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                      -2404267990393.0 / 2016746695238.0, -3550918686646.0 / 2091501179385.0,
+                      -1275806237668.0 / 842570457699.0};
+const double kB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                      1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                      2277821191437.0 / 14882151754819.0};
+
+// Enqueue the 5 stages of one step: stage s reads a, writes b (ping-pong).
+int enqueue_step(esdg_mesh *m, double *q, double *q2, double *dq, double dt, bool start_in_q)
+{
+    StageParams P = base_params(m);
+    P.mode = MODE_STAGE;
+    P.dq = dq;
+    P.dt = dt;
+    double *bufs[2] = {start_in_q ? q : q2, start_in_q ? q2 : q};
+    for (int s = 0; s < 5; ++s) {
+        P.q_in = bufs[s & 1];
+        P.q_out = bufs[(s + 1) & 1];
+        P.A = kA[s];
+        P.B = kB[s];
+        int rc = launch_stage(m, P);
+        if (rc) return rc;
+    }
+    return ESDG_OK;
+}
+
+int check_mesh(esdg_mesh_t m)
+{
+    if (!m) return fail(ESDG_EINVAL, "NULL mesh");
+    return ESDG_OK;
+}
+
+int check_ptr(const void *p, const char *name)
+{
+    if (!p) return fail(ESDG_EINVAL, "%s is NULL", name);
+    if (!aligned8(p)) return fail(ESDG_EINVAL, "%s is not 8-byte aligned", name);
+    return ESDG_OK;
+}
+
+int set_device(esdg_mesh *m)
+{
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != m->device) HIP_TRY(hipSetDevice(m->device));
+    return ESDG_OK;
+}
+
+void drop_graph(esdg_mesh *m)
+{
+    if (m->graph_exec) {
+        (void)hipGraphExecDestroy(m->graph_exec);
+        m->graph_exec = nullptr;
+    }
+    m->g_q = m->g_dq = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *esdg_last_error(void) { return g_err.c_str(); }
+
+const char *esdg_version(void) { return "esdg-gfx950 0.1"; }
+
+int esdg_lgl_tables(int32_t N, double *xi, double *w, double *D)
+{
+    if (N < 1 || N > NQ_MAX - 1) return fail(ESDG_EINVAL, "N=%d outside 1..%d", N, NQ_MAX - 1);
+    if (!xi || !w || !D) return fail(ESDG_EINVAL, "NULL output");
+    lgl_tables(N, xi, w, D);
+    return ESDG_OK;
+}
+
+int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out)
+{
+    if (!d || !out) return fail(ESDG_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (d->N < 1 || d->N > NQ_MAX - 1) return fail(ESDG_EINVAL, "N=%d outside 1..8", d->N);
+    for (int k = 0; k < 3; ++k) {
+        if (d->K[k] < 1) return fail(ESDG_EINVAL, "K[%d]=%d < 1", k, d->K[k]);
+        if (!(d->hi[k] > d->lo[k])) return fail(ESDG_EINVAL, "hi[%d] <= lo[%d]", k, k);
+    }
+    if (d->periodic[2] && d->grav != 0.0)
+        return fail(ESDG_EINVAL, "periodic z with grav != 0 (phi = g z is not periodic)");
+    if (!(d->gamma > 1.0) || !(d->gas_R > 0.0))
+        return fail(ESDG_EINVAL, "gamma must be > 1 and gas_R > 0");
+    if (d->surface_flux != ESDG_SURF_RUSANOV && d->surface_flux != ESDG_SURF_EC)
+        return fail(ESDG_EINVAL, "unknown surface flux %d", d->surface_flux);
+    if (d->precision != ESDG_FP64)
+        return fail(ESDG_ENOTIMPL, "precision %d not available", d->precision);
+    const int epw = d->epw ? d->epw : default_epw(d->N);
+    if (!find_variant(d->N, epw))
+        return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", d->N, epw);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int rc = ensure_tables(dev);
+    if (rc) return rc;
+
+    esdg_mesh *m = new (std::nothrow) esdg_mesh();
+    if (!m) return fail(ESDG_ENOMEM, "host allocation failed");
+    std::memset(m, 0, sizeof *m);
+    m->desc = *d;
+    m->device = dev;
+    m->stream = (hipStream_t)hip_stream;
+    m->N = d->N;
+    m->Nq = d->N + 1;
+    m->Np = m->Nq * m->Nq * m->Nq;
+    m->ne = (int64_t)d->K[0] * d->K[1] * d->K[2];
+    m->nn = m->ne * m->Np;
+    m->state_len = m->nn * 5;
+    m->epw = epw;
+    for (int k = 0; k < 3; ++k) m->h[k] = (d->hi[k] - d->lo[k]) / d->K[k];
+    m->red_blocks = (m->nn + RED_THREADS - 1) / RED_THREADS;
+    const size_t sb = sizeof(double) * (size_t)m->state_len;
+    hipError_t e1 = hipMalloc(&m->d_q2, sb);
+    hipError_t e2 = hipMalloc(&m->d_r, sb);
+    hipError_t e3 = hipMalloc(&m->d_partials, sizeof(double) * 4 * (size_t)m->red_blocks);
+    hipError_t e4 = hipMalloc(&m->d_red_out, sizeof(double) * 4);
+    hipError_t e5 = hipMalloc(&m->d_flag, sizeof(int));
+    hipError_t e6 = hipHostMalloc(&m->h_out, sizeof(double) * 4, hipHostMallocDefault);
+    hipError_t e7 = hipHostMalloc(&m->h_flag, sizeof(int), hipHostMallocDefault);
+    if (e1 || e2 || e3 || e4 || e5 || e6 || e7) {
+        esdg_mesh_destroy(m);
+        return fail(ESDG_ENOMEM, "device allocation of %.1f MB failed", 2.0 * sb / 1e6);
+    }
+    m->footprint = 2 * (int64_t)sb + (int64_t)(sizeof(double) * 4 * m->red_blocks) + 64;
+    hipError_t e8 = hipMemsetAsync(m->d_flag, 0, sizeof(int), m->stream);
+    if (e8 != hipSuccess) {
+        esdg_mesh_destroy(m);
+        return fail(ESDG_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e8));
+    }
+    *out = m;
+    return ESDG_OK;
+}
+
+int esdg_mesh_destroy(esdg_mesh_t m)
+{
+    if (!m) return ESDG_OK;
+    int rc = ESDG_OK;
+    if (m->stream || m->d_q2) {
+        hipError_t e = hipStreamSynchronize(m->stream);
+        if (e != hipSuccess) rc = fail(ESDG_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    drop_graph(m);
+    if (m->d_q2) (void)hipFree(m->d_q2);
+    if (m->d_r) (void)hipFree(m->d_r);
+    if (m->d_partials) (void)hipFree(m->d_partials);
+    if (m->d_red_out) (void)hipFree(m->d_red_out);
+    if (m->d_flag) (void)hipFree(m->d_flag);
+    if (m->h_out) (void)hipHostFree(m->h_out);
+    if (m->h_flag) (void)hipHostFree(m->h_flag);
+    delete m;
+    return rc;
+}
+
+int esdg_mesh_info(esdg_mesh_t m, int64_t *n_elem, int64_t *n_nodes, int64_t *state_len,
+                   int64_t *footprint_bytes)
+{
+    int rc = check_mesh(m);
+    if (rc) return rc;
+    if (n_elem) *n_elem = m->ne;
+    if (n_nodes) *n_nodes = m->nn;
+    if (state_len) *state_len = m->state_len;
+    if (footprint_bytes) *footprint_bytes = m->footprint;
+    return ESDG_OK;
+}
+
+int esdg_set_stream(esdg_mesh_t m, void *hip_stream)
+{
+    int rc = check_mesh(m);
+    if (rc) return rc;
+    m->stream = (hipStream_t)hip_stream;
+    return ESDG_OK;
+}
+
+int esdg_set_epw(esdg_mesh_t m, int32_t epw)
+{
+    int rc = check_mesh(m);
+    if (rc) return rc;
+    const int e = epw ? epw : default_epw(m->N);
+    if (!find_variant(m->N, e)) return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", m->N, e);
+    m->epw = e;
+    drop_graph(m);
+    return ESDG_OK;
+}
+
+int esdg_node_coords(esdg_mesh_t m, double *xyz)
+{
+    int rc = check_mesh(m);
+    if (rc || (rc = check_ptr(xyz, "xyz")) || (rc = set_device(m))) return rc;
+    GeomParams G = geom(m);
+    const int64_t n = m->nn;
+    hipLaunchKernelGGL(node_coords_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       m->stream, G, xyz);
+    HIP_TRY(hipGetLastError());
+    return ESDG_OK;
+}
+
+int esdg_rhs_terms(esdg_mesh_t m, const double *q, double *r, int32_t mask)
+{
+    int rc = check_mesh(m);
+    if (rc || (rc = check_ptr(q, "q")) || (rc = check_ptr(r, "r")) || (rc = set_device(m)))
+        return rc;
+    if (q == r) return fail(ESDG_EINVAL, "q and r must not alias");
+    if (mask & ~ESDG_TERM_ALL) return fail(ESDG_EINVAL, "bad term mask %d", mask);
+    StageParams P = base_params(m);
+    P.mode = MODE_RHS;
+    P.mask = mask;
+    P.q_in = q;
+    P.r_out = r;
+    return launch_stage(m, P);
+}
+
+int esdg_rhs(esdg_mesh_t m, const double *q, double *r, double t)
+{
+    (void)t;
+    return esdg_rhs_terms(m, q, r, ESDG_TERM_ALL);
+}
+
+int esdg_lsrk_step(esdg_mesh_t m, double *q, double *dq, double t, double dt)
+{
+    (void)t;
+    int rc = check_mesh(m);
+    if (rc || (rc = check_ptr(q, "q")) || (rc = check_ptr(dq, "dq")) || (rc = set_device(m)))
+        return rc;
+    if (q == dq) return fail(ESDG_EINVAL, "q and dq must not alias");
+    rc = enqueue_step(m, q, m->d_q2, dq, dt, true);
+    if (rc) return rc;
+    // five stages end in the mesh's second buffer
+    HIP_TRY(hipMemcpyAsync(q, m->d_q2, sizeof(double) * (size_t)m->state_len,
+                           hipMemcpyDeviceToDevice, m->stream));
+    return ESDG_OK;
+}
+
+int esdg_lsrk_run(esdg_mesh_t m, double *q, double *dq, double t0, double dt, int32_t nsteps)
+{
+    int rc = check_mesh(m);
+    if (rc || (rc = check_ptr(q, "q")) || (rc = check_ptr(dq, "dq")) || (rc = set_device(m)))
+        return rc;
+    if (q == dq) return fail(ESDG_EINVAL, "q and dq must not alias");
+    if (nsteps < 0) return fail(ESDG_EINVAL, "nsteps < 0");
+    const int pairs = nsteps / 2;
+    if (pairs > 0) {
+        if (!m->graph_exec || m->g_q != q || m->g_dq != dq || m->g_dt != dt ||
+            m->g_stream != m->stream || m->g_epw != m->epw) {
+            drop_graph(m);
+            // capture two steps (10 stages: q -> q2 -> q -> ... -> q) on a
+            // private stream, then replay on the mesh stream
+            hipStream_t cs;
+            HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipStream_t saved = m->stream;
+            m->stream = cs;
+            hipError_t eb = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            int rc1 = ESDG_OK, rc2 = ESDG_OK;
+            if (eb == hipSuccess) {
+                rc1 = enqueue_step(m, q, m->d_q2, dq, dt, true);
+                if (!rc1) rc2 = enqueue_step(m, q, m->d_q2, dq, dt, false);
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t ee = (eb == hipSuccess) ? hipStreamEndCapture(cs, &graph) : eb;
+            m->stream = saved;
+            (void)hipStreamDestroy(cs);
+            if (eb != hipSuccess) return fail(ESDG_EHIP, "capture: %s", hipGetErrorString(eb));
+            if (rc1 || rc2) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc1 ? rc1 : rc2;
+            }
+            if (ee != hipSuccess) return fail(ESDG_EHIP, "end capture: %s", hipGetErrorString(ee));
+            hipError_t ei = hipGraphInstantiate(&m->graph_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                m->graph_exec = nullptr;
+                return fail(ESDG_EHIP, "graph instantiate: %s", hipGetErrorString(ei));
+            }
+            m->g_q = q;
+            m->g_dq = dq;
+            m->g_dt = dt;
+            m->g_stream = m->stream;
+            m->g_epw = m->epw;
+        }
+        for (int p = 0; p < pairs; ++p) HIP_TRY(hipGraphLaunch(m->graph_exec, m->stream));
+    }
+    if (nsteps & 1) return esdg_lsrk_step(m, q, dq, t0 + dt * (nsteps - 1), dt);
+    return ESDG_OK;
+}
+
+int esdg_check(esdg_mesh_t m)
+{
+    int rc = check_mesh(m);
+    if (rc || (rc = set_device(m))) return rc;
+    HIP_TRY(hipMemcpyAsync(m->h_flag, m->d_flag, sizeof(int), hipMemcpyDeviceToHost, m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    if (*m->h_flag) {
+        HIP_TRY(hipMemsetAsync(m->d_flag, 0, sizeof(int), m->stream));
+        HIP_TRY(hipStreamSynchronize(m->stream));
+        return fail(ESDG_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN) met");
+    }
+    return ESDG_OK;
+}
+
+int esdg_entropy(esdg_mesh_t m, const double *q, double out[4])
+{
+    int rc = check_mesh(m);
+    if (rc || (rc = check_ptr(q, "q")) || (rc = set_device(m))) return rc;
+    if (!out) return fail(ESDG_EINVAL, "out is NULL");
+    rc = esdg_rhs(m, q, m->d_r, 0.0);
+    if (rc) return rc;
+    GeomParams G = geom(m);
+    hipLaunchKernelGGL(entropy_partials_kernel, dim3((unsigned)m->red_blocks), dim3(RED_THREADS),
+                       0, m->stream, G, q, (const double *)m->d_r, m->d_partials, m->d_flag);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(RED_THREADS), 0, m->stream,
+                       (const double *)m->d_partials, (int)m->red_blocks, m->d_red_out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(m->h_out, m->d_red_out, sizeof(double) * 4, hipMemcpyDeviceToHost,
+                           m->stream));
+    rc = esdg_check(m);  // synchronises
+    for (int k = 0; k < 4; ++k) out[k] = m->h_out[k];
+    return rc;
+}
+
+int esdg_cfl_dt(esdg_mesh_t m, const double *q, double cfl, double *dt_out)
+{
+    int rc = check_mesh(m);
+    if (rc || (rc = check_ptr(q, "q")) || (rc = set_device(m))) return rc;
+    if (!dt_out) return fail(ESDG_EINVAL, "dt_out is NULL");
+    GeomParams G = geom(m);
+    hipLaunchKernelGGL(wavespeed_partials_kernel, dim3((unsigned)m->red_blocks),
+                       dim3(RED_THREADS), 0, m->stream, G, q, m->d_partials);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(reduce_max_kernel, dim3(1), dim3(RED_THREADS), 0, m->stream,
+                       (const double *)m->d_partials, (int)m->red_blocks, m->d_red_out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(m->h_out, m->d_red_out, sizeof(double), hipMemcpyDeviceToHost,
+                           m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    const double smax = m->h_out[0];
+    if (!(smax > 0.0) || !std::isfinite(smax))
+        return fail(ESDG_ENONPHYS, "wave speed bound is %g", smax);
+    *dt_out = cfl / ((m->N + 1) * smax);
+    return ESDG_OK;
+}
+
+}  // extern "C"

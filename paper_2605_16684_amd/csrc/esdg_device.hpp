@@ -1,0 +1,635 @@
+// esdg_device.hpp -- device code of the gfx950 ES-DGSEM library (FP64 path).
+//
+// One fused kernel evaluates R(q) of the semi-discrete entropy-stable DGSEM
+// (paper Sec. 3, Eq. nm:semi, in its Jacobian-weighted skew flux-differencing
+// form on affine hexahedra):
+//
+//   R_a = h_a - sum_r (2/h_r) [ sum_{b on the r-line of a} T_{ia ib} F_r(a, b)
+//                               + (1/w_0) F*.n  at face nodes ],
+//   T_ab = S_ab / w_a,  S = W D - (W D)^T,
+//
+// and optionally applies the LSRK(5,4) stage update in the same pass.
+//
+// Work decomposition (designed for wave64, not the paper's thread-per-node
+// layout): one lane owns one LGL line of one element in each direction.  A
+// lane evaluates every unordered node pair (a < b) of its line once and adds
+// both partners' contributions in registers -- the flux-symmetry saving of
+// Sec. 4.1 without the cyclic pair schedule, the antipodal half weights or
+// any cross-lane exchange; the gravity term's partner value is obtained by
+// the scaling G_ba = -G_ab b_a / b_b (Sec. 4.1).  Per-node primitives,
+// reciprocal-free quantities and the per-node logarithms (Sec. 4.1, T2-T4)
+// are computed once per node and staged in LDS.  The three directions run
+// in one launch as three phases (x, y, z) separated by workgroup barriers:
+// the x phase stores its sums in an LDS accumulator, the y phase adds to it,
+// and the z phase -- whose lane owns the nodes (i, j, 0..N) -- finishes R and
+// writes it (or the stage update) with coalesced stores.  Face fluxes are
+// evaluated by the lane that owns the line ending on that face, reading the
+// neighbour's coincident node straight from the stage input.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace esdg {
+
+constexpr int NQ_MAX = 9;  // polynomial order N <= 8
+
+// LGL tables of one order, filled once per device by the host.
+struct OrderTables {
+    double xi[NQ_MAX];
+    double w[NQ_MAX];
+    double winv[NQ_MAX];
+    double T[NQ_MAX][NQ_MAX];  // S_ab / w_a
+};
+
+__constant__ OrderTables c_tab[NQ_MAX];  // index N-1
+
+enum { MODE_RHS = 0, MODE_STAGE = 1 };
+enum { TERM_VOL = 1, TERM_FACE = 2, TERM_SRC = 4 };
+
+struct StageParams {
+    const double *q_in;
+    double *q_out;  // MODE_STAGE
+    double *dq;     // MODE_STAGE
+    double *r_out;  // MODE_RHS
+    int *flag;      // set to 1 on rho <= 0, p <= 0 or NaN
+    int64_t ne;
+    int K[3];
+    int periodic[3];
+    double two_h[3];  // 2 / h_r
+    double zlo, zhi;  // box extent in z (geopotential)
+    double gamma, grav, cor_f;
+    double lnz_scale;  // ln(z/z_s) = ln(z * lnz_scale), z_s = 1/(R * 300 K)
+    double A, B, dt;   // LSRK stage coefficients
+    int mode, mask, surf, nblocks;
+};
+
+// Blocks are dealt to the 8 XCDs round-robin by block id.  Remap so that each
+// XCD walks one contiguous range of elements: x and y neighbours of an
+// element are then processed on the same XCD at nearly the same time and
+// their face traces are served from that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int per = nb >> 3, rem = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * per + (x < rem ? x : rem) + i;
+}
+
+// Per-node quantities staged in LDS.
+struct Node {
+    double r, u0, u1, u2, p, z, lr, lz;  // rho, velocity, pressure, rho/p, logs
+};
+
+template <int R>
+__device__ __forceinline__ double ucomp(const Node &n)
+{
+    return R == 0 ? n.u0 : (R == 1 ? n.u1 : n.u2);
+}
+
+// Log-mean threshold: u = ((b-a)/(b+a))^2 < 1e-4 takes the atanh series.
+constexpr double LM_EPS = 1e-4;
+constexpr double C23 = 2.0 / 3.0, C25 = 2.0 / 5.0, C27 = 2.0 / 7.0;
+
+// {{x}}_log from values and per-node logs.
+__device__ __forceinline__ double log_mean(double xa, double xb, double la, double lb)
+{
+    const double d = xb - xa, s = xa + xb;
+    const double f = d / s;
+    const double u = f * f;
+    if (u < LM_EPS) return s / (2.0 + u * (C23 + u * (C25 + u * C27)));
+    return d / (lb - la);
+}
+
+// 1 / {{x}}_log from values and per-node logs.
+__device__ __forceinline__ double inv_log_mean(double xa, double xb, double la, double lb)
+{
+    const double d = xb - xa, s = xa + xb;
+    const double f = d / s;
+    const double u = f * f;
+    if (u < LM_EPS) return (2.0 + u * (C23 + u * (C25 + u * C27))) / s;
+    return (lb - la) / d;
+}
+
+// Log-means where the logs are only needed on the log branch (face states).
+__device__ __forceinline__ double log_mean_lazy(double xa, double xb, double la)
+{
+    const double d = xb - xa, s = xa + xb;
+    const double f = d / s;
+    const double u = f * f;
+    if (u < LM_EPS) return s / (2.0 + u * (C23 + u * (C25 + u * C27)));
+    return d / (log(xb) - la);
+}
+
+__device__ __forceinline__ double inv_log_mean_lazy(double xa, double xb, double la, double scale)
+{
+    const double d = xb - xa, s = xa + xb;
+    const double f = d / s;
+    const double u = f * f;
+    if (u < LM_EPS) return (2.0 + u * (C23 + u * (C25 + u * C27))) / s;
+    return (log(xb * scale) - la) / d;
+}
+
+// Symmetric part of the two-point flux in direction R between nodes a and b
+// (Sec. 4.1): f^rho = {{rho}}_log {{u_R}};  f^m_c = f^rho {{u_c}} + d_cR {{p}};
+// f^E = f^rho (1/((gamma-1) {{rho/p}}_log) + u_a.u_b/2 + phi_m) +
+//       (p_a u_R,b + p_b u_R,a)/2.   Returns {{rho}}_log for the gravity term.
+template <int R>
+__device__ __forceinline__ double sym_flux(const Node &a, const Node &b, double phi_m,
+                                           double gm1i, double S[5])
+{
+    const double rho_ln = log_mean(a.r, b.r, a.lr, b.lr);
+    const double izln = inv_log_mean(a.z, b.z, a.lz, b.lz);
+    const double uRa = ucomp<R>(a), uRb = ucomp<R>(b);
+    const double frho = rho_ln * 0.5 * (uRa + uRb);
+    S[0] = frho;
+    S[1] = frho * 0.5 * (a.u0 + b.u0);
+    S[2] = frho * 0.5 * (a.u1 + b.u1);
+    S[3] = frho * 0.5 * (a.u2 + b.u2);
+    S[1 + R] += 0.5 * (a.p + b.p);
+    const double uaub = a.u0 * b.u0 + a.u1 * b.u1 + a.u2 * b.u2;
+    S[4] = frho * (izln * gm1i + 0.5 * uaub + phi_m) + 0.5 * (a.p * uRb + b.p * uRa);
+    return rho_ln;
+}
+
+struct Cons {
+    double v[5];
+};
+
+__device__ __forceinline__ void load_cons(const double *__restrict__ q, int64_t e, int np, int n,
+                                          Cons &c)
+{
+    const double *p = q + e * 5 * np + n;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) c.v[v] = p[v * np];
+}
+
+// Normal face flux F*.n for outward normal n = s e_R at a face node with
+// geopotential phi on both sides (the face nodes of neighbours coincide):
+// s * f_R(q-, q+) - lambda/2 (q+ - q-), lambda = max(|u_R| + c) (Rusanov).
+template <int R>
+__device__ __forceinline__ void face_flux(const Cons &qm, const Cons &qp, double phi, double s,
+                                          const StageParams &P, double Fn[5])
+{
+    const double g = P.gamma, gm1 = g - 1.0, gm1i = 1.0 / gm1;
+    Node a, b;
+    {
+        const double r = qm.v[0], ri = 1.0 / r;
+        a.r = r;
+        a.u0 = qm.v[1] * ri;
+        a.u1 = qm.v[2] * ri;
+        a.u2 = qm.v[3] * ri;
+        a.p = gm1 * (qm.v[4] - 0.5 * (qm.v[1] * a.u0 + qm.v[2] * a.u1 + qm.v[3] * a.u2) - r * phi);
+        a.z = r / a.p;
+        a.lr = log(r);
+        a.lz = log(a.z * P.lnz_scale);
+    }
+    {
+        const double r = qp.v[0], ri = 1.0 / r;
+        b.r = r;
+        b.u0 = qp.v[1] * ri;
+        b.u1 = qp.v[2] * ri;
+        b.u2 = qp.v[3] * ri;
+        b.p = gm1 * (qp.v[4] - 0.5 * (qp.v[1] * b.u0 + qp.v[2] * b.u1 + qp.v[3] * b.u2) - r * phi);
+        b.z = r / b.p;
+    }
+    const double rho_ln = log_mean_lazy(a.r, b.r, a.lr);
+    const double izln = inv_log_mean_lazy(a.z, b.z, a.lz, P.lnz_scale);
+    const double uRa = ucomp<R>(a), uRb = ucomp<R>(b);
+    const double frho = rho_ln * 0.5 * (uRa + uRb);
+    double S[5];
+    S[0] = frho;
+    S[1] = frho * 0.5 * (a.u0 + b.u0);
+    S[2] = frho * 0.5 * (a.u1 + b.u1);
+    S[3] = frho * 0.5 * (a.u2 + b.u2);
+    S[1 + R] += 0.5 * (a.p + b.p);
+    const double uaub = a.u0 * b.u0 + a.u1 * b.u1 + a.u2 * b.u2;
+    S[4] = frho * (izln * gm1i + 0.5 * uaub + phi) + 0.5 * (a.p * uRb + b.p * uRa);
+    double lam = 0.0;
+    if (P.surf == 0) {
+        const double la = fabs(uRa) + sqrt(g * a.p / a.r);
+        const double lb = fabs(uRb) + sqrt(g * b.p / b.r);
+        lam = la > lb ? la : lb;
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fn[v] = s * S[v] - 0.5 * lam * (qp.v[v] - qm.v[v]);
+}
+
+// Node index of position t along the R-line owned by lane m.
+template <int NQ, int R>
+__device__ __forceinline__ int line_node(int m, int t)
+{
+    constexpr int NQ2 = NQ * NQ;
+    if (R == 0) return t + NQ * m;                              // m = j + NQ k
+    if (R == 1) return (m % NQ) + NQ * t + NQ2 * (m / NQ);      // m = i + NQ k
+    return m + NQ2 * t;                                         // m = i + NQ j
+}
+
+// Volume pairs and face terms of one line in direction R; acc receives the
+// unscaled sums (the caller multiplies by 2/h_R).
+template <int NQ, int EPW, int R>
+__device__ __forceinline__ void line_terms(const double (*__restrict__ st)[EPW][NQ * NQ * NQ],
+                                           const StageParams &P, const OrderTables &tb, int el,
+                                           int m, int64_t e, const int ec[3],
+                                           const double phi_k[NQ], double acc[NQ][5])
+{
+    constexpr int NQ3 = NQ * NQ * NQ;
+    const double gm1i = 1.0 / (P.gamma - 1.0);
+#pragma unroll
+    for (int a = 0; a < NQ; ++a)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[a][v] = 0.0;
+
+    // issue the face-neighbour loads first: their latency hides behind the pairs
+    Cons qm[2], qp[2];
+    const bool faces = (P.mask & TERM_FACE) != 0;
+    if (faces) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int t = side ? NQ - 1 : 0;
+            const int n = line_node<NQ, R>(m, t);
+            load_cons(P.q_in, e, NQ3, n, qm[side]);
+            int nb = ec[R] + (side ? 1 : -1);
+            const bool wall = (nb < 0 || nb >= P.K[R]) && !P.periodic[R];
+            if (wall) {
+                qp[side] = qm[side];
+                qp[side].v[1 + R] = -qp[side].v[1 + R];
+            } else {
+                if (nb < 0) nb += P.K[R];
+                if (nb >= P.K[R]) nb -= P.K[R];
+                int cc[3] = {ec[0], ec[1], ec[2]};
+                cc[R] = nb;
+                const int64_t en = cc[0] + (int64_t)P.K[0] * (cc[1] + (int64_t)P.K[1] * cc[2]);
+                const int nn = line_node<NQ, R>(m, side ? 0 : NQ - 1);
+                load_cons(P.q_in, en, NQ3, nn, qp[side]);
+            }
+        }
+    }
+
+    if (P.mask & TERM_VOL) {
+        Node nd[NQ];
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const int n = line_node<NQ, R>(m, t);
+            nd[t].r = st[0][el][n];
+            nd[t].u0 = st[1][el][n];
+            nd[t].u1 = st[2][el][n];
+            nd[t].u2 = st[3][el][n];
+            nd[t].p = st[4][el][n];
+            nd[t].z = st[5][el][n];
+            nd[t].lr = st[6][el][n];
+            nd[t].lz = st[7][el][n];
+        }
+        double zinv[NQ];
+        if (R == 2) {
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) zinv[t] = nd[t].p / nd[t].r;
+        }
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+#pragma unroll
+            for (int b = a + 1; b < NQ; ++b) {
+                const double phi_m = R == 2 ? 0.5 * (phi_k[a] + phi_k[b]) : phi_k[0];
+                double S[5];
+                const double rho_ln = sym_flux<R>(nd[a], nd[b], phi_m, gm1i, S);
+                const double tab = tb.T[a][b], tba = tb.T[b][a];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    acc[a][v] -= tab * S[v];
+                    acc[b][v] -= tba * S[v];
+                }
+                if (R == 2) {
+                    // gravity term G_ab = rho_hat [[phi]]/2, rho_hat = {{b}} {{rho}}_log / b_a,
+                    // b = z/2; partner: G_ba = -G_ab z_a / z_b
+                    const double X = 0.25 * rho_ln * (nd[a].z + nd[b].z) * (phi_k[b] - phi_k[a]);
+                    acc[a][3] -= tab * (X * zinv[a]);
+                    acc[b][3] -= tba * (-X * zinv[b]);
+                }
+            }
+        }
+    }
+
+    if (faces) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int t = side ? NQ - 1 : 0;
+            double Fn[5];
+            face_flux<R>(qm[side], qp[side], R == 2 ? phi_k[t] : phi_k[0], side ? 1.0 : -1.0, P,
+                         Fn);
+            const double wi = tb.winv[t];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[t][v] -= wi * Fn[v];
+        }
+    }
+}
+
+template <int NQ, int EPW>
+constexpr int block_threads()
+{
+    return ((EPW * NQ * NQ + 63) / 64) * 64;
+}
+
+template <int NQ, int EPW>
+__global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const StageParams P)
+{
+    constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
+    __shared__ double st[8][EPW][NQ3];
+    __shared__ double sacc[5][EPW][NQ3];
+
+    const OrderTables &tb = c_tab[NQ - 2];
+    const int tid = threadIdx.x;
+    const int el = tid / NQ2;
+    const int m = tid - el * NQ2;
+    const int lb = xcd_remap(blockIdx.x, P.nblocks);
+    const int64_t e = (int64_t)lb * EPW + el;
+    const bool act = (el < EPW) && (e < P.ne);
+
+    int ec[3] = {0, 0, 0};
+    if (act) {
+        ec[0] = (int)(e % P.K[0]);
+        const int64_t t = e / P.K[0];
+        ec[1] = (int)(t % P.K[1]);
+        ec[2] = (int)(t / P.K[1]);
+    }
+    // geopotential at the nodes of this element's z-levels
+    double phi_k[NQ];
+    {
+        const double dz = P.zhi - P.zlo;
+        const double ZL = P.zlo + dz * ((double)ec[2] / (double)P.K[2]);
+        const double ZR = P.zlo + dz * ((double)(ec[2] + 1) / (double)P.K[2]);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const double s = tb.xi[k];
+            phi_k[k] = P.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
+        }
+    }
+
+    // phase 0: per-node primitives and logarithms into LDS (lane m = (i, j)
+    // handles the nodes (i, j, 0..N): coalesced loads across lanes)
+    if (act) {
+        const double gm1 = P.gamma - 1.0;
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int n = m + NQ2 * k;
+            Cons c;
+            load_cons(P.q_in, e, NQ3, n, c);
+            const double r = c.v[0], ri = 1.0 / r;
+            const double u0 = c.v[1] * ri, u1 = c.v[2] * ri, u2 = c.v[3] * ri;
+            const double p =
+                gm1 * (c.v[4] - 0.5 * (c.v[1] * u0 + c.v[2] * u1 + c.v[3] * u2) - r * phi_k[k]);
+            const double z = r / p;
+            bad |= !(r > 0.0) || !(p > 0.0);
+            st[0][el][n] = r;
+            st[1][el][n] = u0;
+            st[2][el][n] = u1;
+            st[3][el][n] = u2;
+            st[4][el][n] = p;
+            st[5][el][n] = z;
+            st[6][el][n] = log(r);
+            st[7][el][n] = log(z * P.lnz_scale);
+        }
+        if (bad) atomicOr(P.flag, 1);
+    }
+    __syncthreads();
+
+    double acc[NQ][5];
+    const bool vol_or_face = (P.mask & (TERM_VOL | TERM_FACE)) != 0;
+
+    // x phase: lane m = (j, k)
+    if (act && vol_or_face) {
+        double phl[NQ];
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
+        line_terms<NQ, EPW, 0>(st, P, tb, el, m, e, ec, phl, acc);
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const int n = line_node<NQ, 0>(m, t);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sacc[v][el][n] = P.two_h[0] * acc[t][v];
+        }
+    } else if (act) {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const int n = line_node<NQ, 0>(m, t);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sacc[v][el][n] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    // y phase: lane m = (i, k)
+    if (act && vol_or_face) {
+        double phl[NQ];
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
+        line_terms<NQ, EPW, 1>(st, P, tb, el, m, e, ec, phl, acc);
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const int n = line_node<NQ, 1>(m, t);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sacc[v][el][n] += P.two_h[1] * acc[t][v];
+        }
+    }
+    __syncthreads();
+
+    // z phase: lane m = (i, j) owns the nodes (i, j, 0..N) and finishes them
+    if (!act) return;
+    if (vol_or_face) {
+        line_terms<NQ, EPW, 2>(st, P, tb, el, m, e, ec, phi_k, acc);
+    } else {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[t][v] = 0.0;
+    }
+    const bool src = (P.mask & TERM_SRC) != 0;
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+        const int n = m + NQ2 * t;
+        double Rv[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Rv[v] = sacc[v][el][n] + P.two_h[2] * acc[t][v];
+        const int64_t base = e * 5 * NQ3 + n;
+        if (src) {
+            const double m1 = P.q_in[base + 1 * NQ3], m2 = P.q_in[base + 2 * NQ3];
+            Rv[1] += P.cor_f * m2;
+            Rv[2] -= P.cor_f * m1;
+        }
+        if (P.mode == MODE_RHS) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) P.r_out[base + v * NQ3] = Rv[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double d = P.A * P.dq[base + v * NQ3] + P.dt * Rv[v];
+                P.dq[base + v * NQ3] = d;
+                P.q_out[base + v * NQ3] = P.q_in[base + v * NQ3] + P.B * d;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Auxiliary kernels: node coordinates, diagnostics, time-step bound.
+// ---------------------------------------------------------------------------
+
+struct GeomParams {
+    int64_t ne;
+    int N;
+    int K[3];
+    double lo[3], hi[3];
+    double h[3];
+    double gamma, grav, lnz_scale;
+};
+
+__device__ __forceinline__ double vertex(const GeomParams &G, int d, int e)
+{
+    return G.lo[d] + (G.hi[d] - G.lo[d]) * ((double)e / (double)G.K[d]);
+}
+
+__global__ void node_coords_kernel(const GeomParams G, double *__restrict__ xyz)
+{
+    const int NQ = G.N + 1, NP = NQ * NQ * NQ;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= G.ne * NP) return;
+    const int64_t e = gid / NP;
+    const int n = (int)(gid - e * NP);
+    const int ii[3] = {n % NQ, (n / NQ) % NQ, n / (NQ * NQ)};
+    const int ec[3] = {(int)(e % G.K[0]), (int)((e / G.K[0]) % G.K[1]),
+                       (int)(e / ((int64_t)G.K[0] * G.K[1]))};
+    const OrderTables &tb = c_tab[G.N - 1];
+    for (int d = 0; d < 3; ++d) {
+        const double s = tb.xi[ii[d]];
+        const double XL = vertex(G, d, ec[d]), XR = vertex(G, d, ec[d] + 1);
+        xyz[(e * 3 + d) * NP + n] = 0.5 * (1.0 - s) * XL + 0.5 * (1.0 + s) * XR;
+    }
+}
+
+constexpr int RED_THREADS = 256;
+
+// Per-block partial sums of J w (eta, rho, E, v.R) over nodes; deterministic
+// fixed-shape tree within the block.  r may be NULL (then v.R = 0).
+__global__ void __launch_bounds__(RED_THREADS)
+    entropy_partials_kernel(const GeomParams G, const double *__restrict__ q,
+                            const double *__restrict__ r, double *__restrict__ partials,
+                            int *flag)
+{
+    __shared__ double sh[4][RED_THREADS];
+    const int NQ = G.N + 1, NP = NQ * NQ * NQ;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (gid < G.ne * NP) {
+        const int64_t e = gid / NP;
+        const int n = (int)(gid - e * NP);
+        const int i = n % NQ, j = (n / NQ) % NQ, k = n / (NQ * NQ);
+        const OrderTables &tb = c_tab[G.N - 1];
+        const int ez = (int)(e / ((int64_t)G.K[0] * G.K[1]));
+        const double s = tb.xi[k];
+        const double ZL = vertex(G, 2, ez), ZR = vertex(G, 2, ez + 1);
+        const double phi = G.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
+        const double J = G.h[0] * G.h[1] * G.h[2] * 0.125;
+        const double wq = J * tb.w[i] * tb.w[j] * tb.w[k];
+        const int64_t base = e * 5 * NP + n;
+        const double rho = q[base], m0 = q[base + NP], m1 = q[base + 2 * NP],
+                     m2 = q[base + 3 * NP], E = q[base + 4 * NP];
+        const double ri = 1.0 / rho;
+        const double u0 = m0 * ri, u1 = m1 * ri, u2 = m2 * ri;
+        const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+        const double p = (G.gamma - 1.0) * (E - 0.5 * rho * uu - rho * phi);
+        if (!(rho > 0.0) || !(p > 0.0)) atomicOr(flag, 1);
+        const double ent = log(p) - G.gamma * log(rho);
+        const double b = 0.5 * rho / p;
+        s0 = wq * (-rho * ent / (G.gamma - 1.0));
+        s1 = wq * rho;
+        s2 = wq * E;
+        if (r) {
+            const double v0 = (G.gamma - ent) / (G.gamma - 1.0) - b * uu + 2.0 * b * phi;
+            s3 = wq * (v0 * r[base] + 2.0 * b * (u0 * r[base + NP] + u1 * r[base + 2 * NP] +
+                                                 u2 * r[base + 3 * NP]) -
+                       2.0 * b * r[base + 4 * NP]);
+        }
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    sh[2][threadIdx.x] = s2;
+    sh[3][threadIdx.x] = s3;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partials[(int64_t)blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Sum nb partial 4-vectors in a fixed order into out[0..3].
+__global__ void __launch_bounds__(RED_THREADS)
+    reduce_partials_kernel(const double *__restrict__ partials, int nb, double *__restrict__ out)
+{
+    __shared__ double sh[4][RED_THREADS];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS)
+        for (int c = 0; c < 4; ++c) s[c] += partials[(int64_t)b * 4 + c];
+    for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Per-block maxima of sum_r (|u_r| + c)/h_r.
+__global__ void __launch_bounds__(RED_THREADS)
+    wavespeed_partials_kernel(const GeomParams G, const double *__restrict__ q,
+                              double *__restrict__ partials)
+{
+    __shared__ double sh[RED_THREADS];
+    const int NQ = G.N + 1, NP = NQ * NQ * NQ;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double smax = 0.0;
+    if (gid < G.ne * NP) {
+        const int64_t e = gid / NP;
+        const int n = (int)(gid - e * NP);
+        const int k = n / (NQ * NQ);
+        const OrderTables &tb = c_tab[G.N - 1];
+        const int ez = (int)(e / ((int64_t)G.K[0] * G.K[1]));
+        const double s = tb.xi[k];
+        const double ZL = vertex(G, 2, ez), ZR = vertex(G, 2, ez + 1);
+        const double phi = G.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
+        const int64_t base = e * 5 * NP + n;
+        const double rho = q[base];
+        const double u[3] = {q[base + NP] / rho, q[base + 2 * NP] / rho, q[base + 3 * NP] / rho};
+        const double p = (G.gamma - 1.0) *
+                         (q[base + 4 * NP] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
+                          rho * phi);
+        const double c = sqrt(G.gamma * p / rho);
+        smax = (fabs(u[0]) + c) / G.h[0] + (fabs(u[1]) + c) / G.h[1] + (fabs(u[2]) + c) / G.h[2];
+        if (!(smax == smax)) smax = INFINITY;
+    }
+    sh[threadIdx.x] = smax;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(RED_THREADS)
+    reduce_max_kernel(const double *__restrict__ partials, int nb, double *__restrict__ out)
+{
+    __shared__ double sh[RED_THREADS];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS) s = fmax(s, partials[b]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+}  // namespace esdg

@@ -1,0 +1,63 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+entry point include/esdg.h declares; host-only pieces are checked here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "esdg.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(esdg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("esdg_mesh_create", "esdg_rhs", "esdg_lsrk_step", "esdg_entropy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2605_16684_amd import esdg
+    lib = C.CDLL(esdg.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert name in esdg.SIGNATURES, name
+    assert set(esdg.SIGNATURES) == set(_declared())
+
+
+@pytest.mark.parametrize("N", range(1, 9))
+def test_library_lgl_tables_match_oracle(N):
+    from paper_2605_16684_amd import esdg
+    x, w, D = esdg.lgl_tables(N)
+    xo, wo, Do = O.lgl(N)
+    assert np.max(np.abs(x - xo)) <= 2.3e-16
+    assert np.max(np.abs(w - wo)) <= 4.5e-16
+    assert np.max(np.abs(D - Do)) <= 1e-13 * N * N
+
+
+def test_invalid_arguments_fail_without_touching_the_device():
+    from paper_2605_16684_amd import esdg
+    d = esdg.MeshDesc()
+    d.N = 0
+    d.K[:] = [1, 1, 1]
+    d.hi[:] = [1.0, 1.0, 1.0]
+    d.gamma, d.gas_R = 1.4, 287.0
+    h = C.c_void_p()
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    assert "N=0" in esdg.last_error()
+    d.N = 4
+    d.periodic[:] = [0, 0, 1]
+    d.grav = 9.81
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    assert "periodic z" in esdg.last_error()
+    assert esdg.lib.esdg_rhs(None, None, None, 0.0) == esdg.ESDG_EINVAL
+    assert esdg.lib.esdg_lgl_tables(9, None, None, None) == esdg.ESDG_EINVAL
