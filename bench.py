@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the ES-DGSEM hot path on one MI355X.
+
+One step = one LSRK(5,4) time step = five fused stage kernels (per-node
+precompute, flux-differencing volume term with the gravity two-point term,
+face Riemann flux and lift, Coriolis source, stage update) over the whole
+mesh, replayed from a captured HIP graph.  The metric is DOF*RHS/s: nodes x
+right-hand-side evaluations per second (DOF = N_e (N+1)^3 nodes; one step =
+5 RHS).  Inputs are seeded synthetic states already resident in HBM.
+
+Prints ONE JSON line on stdout (everything else goes to stderr).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_record(kernel_name, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
+    the kernel sources changed since the counters were taken."""
+    from paper_2605_16684_amd import perfmodel
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    ent = rec.get(workload, {}).get(kernel_name)
+    if not ent or ent.get("kernel_hash") != perfmodel.kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, seconds, seed=1):
+    """The oracle (plain FP64 C, OpenMP, full ordered-pair loop) timed on a
+    bounded sample of the same workload: RHS evaluations of a fixed block of
+    elements, repeated for about `seconds`."""
+    import numpy as np
+    import oracle as O
+    from paper_2605_16684_amd import workloads as W
+    s = wl.mesh
+    om = O.Mesh(s.N, s.K, s.lo, s.hi, s.periodic, gamma=s.gamma, gas_R=s.gas_R, grav=s.grav,
+                coriolis_f=s.coriolis_f, surface_flux=s.surface_flux)
+    q = W.make_state(wl.kind, om.coords(), s, seed=seed)
+    n_el = min(om.ne, 2048)
+    elems = np.arange(n_el, dtype=np.int64)
+    om.rhs_elems(q, elems)  # warm
+    t0 = time.perf_counter()
+    evals = 0
+    while True:
+        om.rhs_elems(q, elems)
+        evals += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    nodes = n_el * om.Np
+    return {"value": nodes * evals / el, "unit": "DOF*RHS/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{evals} RHS evaluations of elements 0..{n_el - 1} ({nodes} nodes) of "
+                      f"{wl.name}, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c1", help="c0 | c1 | c2 | c3")
+    ap.add_argument("--epw", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain copy of known size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the mesh would shard by element slabs with face-trace exchange; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        sys.exit("bench.py: --steps must be >= 1 and --warmup >= 0")
+
+    import numpy as np
+    import torch
+    from paper_2605_16684_amd import esdg, perfmodel
+    from paper_2605_16684_amd import workloads as W
+
+    wl = W.WORKLOADS[args.workload]
+    spec = wl.mesh
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    mesh = esdg.Mesh(spec, epw=args.epw)
+    xyz = mesh.coords().cpu().numpy()
+    q0 = W.make_state(wl.kind, xyz, spec, seed=1)
+    del xyz
+    q = torch.from_numpy(q0).cuda()
+    del q0
+    dq = torch.zeros_like(q)
+    dt = mesh.cfl_dt(q, wl.cfl)
+    diag0 = mesh.entropy(q)
+    log(f"[bench] {wl.name}: {mesh.n_elem} elements, {mesh.n_nodes} nodes, dt={dt:.4e} s")
+
+    # warm-up (also captures the two-step graph)
+    if args.warmup:
+        mesh.lsrk_run(q, dq, dt, args.warmup)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    mesh.lsrk_run(q, dq, dt, K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    mesh.check()
+    diag1 = mesh.entropy(q)
+
+    nn = mesh.n_nodes
+    value = nn * 5.0 * K / (ms * 1e-3)
+    # the timed region holds only fused stage launches when K is even
+    launches = 5 * K
+    t_launch = ms * 1e-3 / launches
+    N = spec.N
+    bytes_launch = perfmodel.bytes_per_node(N, stage=True) * nn
+    flops_launch = perfmodel.flops_per_node(N, stage=True) * nn
+    achieved_gbs = bytes_launch / t_launch / 1e9
+    achieved_tf = flops_launch / t_launch / 1e12
+    kname = f"stage_fp64<{N + 1},{mesh.epw}>"
+    traffic = traffic_record("stage_fp64", wl.name)
+
+    # RHS-only launches (no update), for the per-kernel table
+    r = torch.empty_like(q)
+    for _ in range(3):
+        mesh.rhs(q, r)
+    torch.cuda.synchronize()
+    nr = 20
+    e0.record(stream)
+    for _ in range(nr):
+        mesh.rhs(q, r)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_rhs = e0.elapsed_time(e1) * 1e-3 / nr
+
+    if args.calib_copy:
+        n = 1 << 27  # 1 GiB of doubles
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            esdg.copy(a, b)
+        torch.cuda.synchronize()
+        del a, b
+
+    out = {
+        "metric": "DOF*RHS/s (FP64 ES-DGSEM right-hand side, LSRK(5,4) steps)",
+        "value": value,
+        "unit": "DOF*RHS/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "N": N, "K": list(spec.K), "n_elem": mesh.n_elem,
+                   "nodes": nn, "dt": dt, "cfl": wl.cfl, "surface_flux": "rusanov",
+                   "epw": mesh.epw, "step": "5 fused stage kernels (hipGraph)"},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": perfmodel.HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_gbs / perfmodel.HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": kname,
+                     "launch_ms": t_launch * 1e3,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "algorithmic_flops_per_launch": flops_launch,
+                     "fp64_tflops": achieved_tf,
+                     "fp64_frac": achieved_tf / perfmodel.FP64_VECTOR_TFLOPS},
+        "rhs_only": {"launch_ms": t_rhs * 1e3, "dof_rhs_per_s": nn / t_rhs,
+                     "gbs": perfmodel.bytes_per_node(N, stage=False) * nn / t_rhs / 1e9,
+                     "fp64_tflops": perfmodel.flops_per_node(N, stage=False) * nn / t_rhs / 1e12},
+        "conservation": {"mass_rel_drift": abs(diag1[1] - diag0[1]) / abs(diag0[1]),
+                         "energy_rel_drift": abs(diag1[2] - diag0[2]) / abs(diag0[2]),
+                         "entropy_rel_change": (diag1[0] - diag0[0]) / abs(diag0[0])},
+        "cpu_baseline": None,
+    }
+    mesh.close()
+    del q, dq, r
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,13 +109,16 @@ int esdg_set_stream(esdg_mesh_t mesh, void *hip_stream);
  * default.  ESDG_EINVAL if the value has no compiled variant. */
 int esdg_set_epw(esdg_mesh_t mesh, int32_t epw);
 
+/* Elements per workgroup currently used by the mesh's launches. */
+int esdg_get_epw(esdg_mesh_t mesh, int32_t *epw);
+
 /* Node coordinates into xyz_dev[e][3][n] (device, caller owned). */
 int esdg_node_coords(esdg_mesh_t mesh, double *xyz_dev);
 
 /* r = R(q): the full semi-discrete right-hand side of Eq. (nm:semi) --
  * flux-differencing volume term with the entropy-conservative two-point
  * flux and its gravity term, face flux and lift, Coriolis source.  q and r
- * are device arrays of state_len doubles and must not overlap.  t is the
+ * are device arrays of state_len doubles and must not overlap (ESDG_EINVAL).  t is the
  * time (the operator is autonomous; kept for the dq/dt = R(q, t) form). */
 int esdg_rhs(esdg_mesh_t mesh, const double *q_dev, double *r_dev, double t);
 
@@ -152,6 +155,12 @@ int esdg_cfl_dt(esdg_mesh_t mesh, const double *q_dev, double cfl, double *dt_ou
 /* Synchronise and report ESDG_ENONPHYS if any kernel met rho <= 0, p <= 0
  * or NaN since the last check (the flag is cleared). */
 int esdg_check(esdg_mesh_t mesh);
+
+/* dst[i] = src[i] for i < n doubles with a plain vectorised copy kernel on
+ * `hip_stream` (device pointers, caller owned, must not overlap).  Used to
+ * snapshot states and to calibrate hardware byte counters against a copy
+ * of known size (reads 8n bytes, writes 8n bytes). */
+int esdg_copy(const double *src, double *dst, int64_t n, void *hip_stream);
 
 /* Thread-local text of the last error in this thread ("" if none). */
 const char *esdg_last_error(void);

@@ -157,6 +157,13 @@ int ensure_tables(int dev)
 
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
+// Two arrays of n doubles overlap.
+bool overlaps(const double *a, const double *b, int64_t n)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b, len = (uintptr_t)n * sizeof(double);
+    return x < y + len && y < x + len;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -196,10 +203,12 @@ typedef void (*stage_kernel_t)(StageParams);
 
 struct Variant {
     int N, epw, threads;
-    stage_kernel_t fn;
+    stage_kernel_t rhs, stage;
 };
 
-#define V(NN, E) {NN, E, block_threads<NN + 1, E>(), stage_fp64<NN + 1, E>}
+#define V(NN, E)                                                                             \
+    {NN, E, block_threads<NN + 1, E>(), stage_fp64<NN + 1, E, MODE_RHS>,                    \
+     stage_fp64<NN + 1, E, MODE_STAGE>}
 const Variant kVariants[] = {
     V(1, 8), V(1, 16), V(1, 32),
     V(2, 4), V(2, 7), V(2, 14),
@@ -225,7 +234,7 @@ int default_epw(int N)
     case 1: return 16;
     case 2: return 7;
     case 3: return 4;
-    case 4: return 5;
+    case 4: return 2;
     case 5: return 3;
     case 6: return 2;
     case 7: return 1;
@@ -279,7 +288,8 @@ int launch_stage(esdg_mesh *m, StageParams P)
     const int64_t nb = (m->ne + m->epw - 1) / m->epw;
     if (nb > 0x7fffffff) return fail(ESDG_EINVAL, "mesh too large");
     P.nblocks = (int)nb;
-    hipLaunchKernelGGL(v->fn, dim3((unsigned)nb), dim3(v->threads), 0, m->stream, P);
+    hipLaunchKernelGGL(P.mode == MODE_RHS ? v->rhs : v->stage, dim3((unsigned)nb),
+                       dim3(v->threads), 0, m->stream, P);
     HIP_TRY(hipGetLastError());
     return ESDG_OK;
 }
@@ -358,6 +368,30 @@ int esdg_lgl_tables(int32_t N, double *xi, double *w, double *D)
     if (N < 1 || N > NQ_MAX - 1) return fail(ESDG_EINVAL, "N=%d outside 1..%d", N, NQ_MAX - 1);
     if (!xi || !w || !D) return fail(ESDG_EINVAL, "NULL output");
     lgl_tables(N, xi, w, D);
+    return ESDG_OK;
+}
+
+int esdg_copy(const double *src, double *dst, int64_t n, void *hip_stream)
+{
+    if (n < 0) return fail(ESDG_EINVAL, "n < 0");
+    if (n == 0) return ESDG_OK;
+    int rc;
+    if ((rc = check_ptr(src, "src")) || (rc = check_ptr(dst, "dst"))) return rc;
+    if (((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u))
+        return fail(ESDG_EINVAL, "src/dst must be 16-byte aligned");
+    if ((src < dst + n) && (dst < src + n)) return fail(ESDG_EINVAL, "src and dst overlap");
+    const int64_t n2 = n / 2;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (n2 > 0) {
+        const int64_t blocks = std::min<int64_t>((n2 + 255) / 256, 256 * 64);
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const double2 *)src, (double2 *)dst, n2);
+        HIP_TRY(hipGetLastError());
+    }
+    if (n & 1) {
+        hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(64), 0, s, src, dst, n);
+        HIP_TRY(hipGetLastError());
+    }
     return ESDG_OK;
 }
 
@@ -474,6 +508,15 @@ int esdg_set_epw(esdg_mesh_t m, int32_t epw)
     return ESDG_OK;
 }
 
+int esdg_get_epw(esdg_mesh_t m, int32_t *epw)
+{
+    int rc = check_mesh(m);
+    if (rc) return rc;
+    if (!epw) return fail(ESDG_EINVAL, "epw is NULL");
+    *epw = m->epw;
+    return ESDG_OK;
+}
+
 int esdg_node_coords(esdg_mesh_t m, double *xyz)
 {
     int rc = check_mesh(m);
@@ -491,7 +534,7 @@ int esdg_rhs_terms(esdg_mesh_t m, const double *q, double *r, int32_t mask)
     int rc = check_mesh(m);
     if (rc || (rc = check_ptr(q, "q")) || (rc = check_ptr(r, "r")) || (rc = set_device(m)))
         return rc;
-    if (q == r) return fail(ESDG_EINVAL, "q and r must not alias");
+    if (overlaps(q, r, m->state_len)) return fail(ESDG_EINVAL, "q and r must not overlap");
     if (mask & ~ESDG_TERM_ALL) return fail(ESDG_EINVAL, "bad term mask %d", mask);
     StageParams P = base_params(m);
     P.mode = MODE_RHS;
@@ -513,7 +556,7 @@ int esdg_lsrk_step(esdg_mesh_t m, double *q, double *dq, double t, double dt)
     int rc = check_mesh(m);
     if (rc || (rc = check_ptr(q, "q")) || (rc = check_ptr(dq, "dq")) || (rc = set_device(m)))
         return rc;
-    if (q == dq) return fail(ESDG_EINVAL, "q and dq must not alias");
+    if (overlaps(q, dq, m->state_len)) return fail(ESDG_EINVAL, "q and dq must not overlap");
     rc = enqueue_step(m, q, m->d_q2, dq, dt, true);
     if (rc) return rc;
     // five stages end in the mesh's second buffer
@@ -527,7 +570,7 @@ int esdg_lsrk_run(esdg_mesh_t m, double *q, double *dq, double t0, double dt, in
     int rc = check_mesh(m);
     if (rc || (rc = check_ptr(q, "q")) || (rc = check_ptr(dq, "dq")) || (rc = set_device(m)))
         return rc;
-    if (q == dq) return fail(ESDG_EINVAL, "q and dq must not alias");
+    if (overlaps(q, dq, m->state_len)) return fail(ESDG_EINVAL, "q and dq must not overlap");
     if (nsteps < 0) return fail(ESDG_EINVAL, "nsteps < 0");
     const int pairs = nsteps / 2;
     if (pairs > 0) {

@@ -75,9 +75,11 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * per + (x < rem ? x : rem) + i;
 }
 
-// Per-node quantities staged in LDS.
+// Per-node quantities staged in LDS (one double each): density, velocity,
+// pressure, z = rho/p (= 2b) and its reciprocal p/rho.
+constexpr int NST = 7;
 struct Node {
-    double r, u0, u1, u2, p, z, lr, lz;  // rho, velocity, pressure, rho/p, logs
+    double r, u0, u1, u2, p, z, zi;
 };
 
 template <int R>
@@ -86,47 +88,53 @@ __device__ __forceinline__ double ucomp(const Node &n)
     return R == 0 ? n.u0 : (R == 1 ? n.u1 : n.u2);
 }
 
-// Log-mean threshold: u = ((b-a)/(b+a))^2 < 1e-4 takes the atanh series.
-constexpr double LM_EPS = 1e-4;
-constexpr double C23 = 2.0 / 3.0, C25 = 2.0 / 5.0, C27 = 2.0 / 7.0;
+// a/b by Newton-Raphson refinement of the hardware reciprocal estimate
+// (two Newton steps on 1/b, then one residual correction of the quotient;
+// Markstein's scheme).  For the normal, finite operands met here it agrees
+// with the IEEE quotient; it skips the range scaling and special-value
+// fix-up of the full division sequence.
+__device__ __forceinline__ double fdiv(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    const double q = a * r;
+    const double rem = fma(-b, q, a);
+    return fma(rem, r, q);
+}
 
-// {{x}}_log from values and per-node logs.
+// Log-mean branch rule: u = ((b-a)/(b+a))^2 < 1e-4 takes the series.
+constexpr double LM_EPS = 1e-4;
+// The per-line test that decides whether a line needs per-node logarithms
+// is slightly tighter, so that a line declared log-free never has a pair
+// whose own test selects the log branch.
+constexpr double LM_EPS_LINE = 0.999e-4;
+// {{x}}_log = (a+b)/2 * f/atanh(f), f/atanh(f) = 1 - u/3 - 4u^2/45 - 44u^3/945 - ...
+constexpr double S1 = 1.0 / 3.0, S2 = 4.0 / 45.0, S3 = 44.0 / 945.0;
+// 1/{{x}}_log = 2/(a+b) * atanh(f)/f,  atanh(f)/f = 1 + u/3 + u^2/5 + u^3/7 + ...
+constexpr double I1 = 1.0 / 3.0, I2 = 1.0 / 5.0, I3 = 1.0 / 7.0;
+
+// {{x}}_log with one division: series x = d/s, else x = d/(ln b - ln a).
 __device__ __forceinline__ double log_mean(double xa, double xb, double la, double lb)
 {
     const double d = xb - xa, s = xa + xb;
-    const double f = d / s;
-    const double u = f * f;
-    if (u < LM_EPS) return s / (2.0 + u * (C23 + u * (C25 + u * C27)));
-    return d / (lb - la);
+    const bool ser = d * d < LM_EPS * (s * s);
+    const double x = fdiv(d, ser ? s : lb - la);
+    const double u = x * x;
+    return ser ? 0.5 * s * (1.0 - u * (S1 + u * (S2 + u * S3))) : x;
 }
 
-// 1 / {{x}}_log from values and per-node logs.
+// 1/{{x}}_log with one division: series x = 1/s, else x = (ln b - ln a)/d.
 __device__ __forceinline__ double inv_log_mean(double xa, double xb, double la, double lb)
 {
     const double d = xb - xa, s = xa + xb;
-    const double f = d / s;
-    const double u = f * f;
-    if (u < LM_EPS) return (2.0 + u * (C23 + u * (C25 + u * C27))) / s;
-    return (lb - la) / d;
-}
-
-// Log-means where the logs are only needed on the log branch (face states).
-__device__ __forceinline__ double log_mean_lazy(double xa, double xb, double la)
-{
-    const double d = xb - xa, s = xa + xb;
-    const double f = d / s;
-    const double u = f * f;
-    if (u < LM_EPS) return s / (2.0 + u * (C23 + u * (C25 + u * C27)));
-    return d / (log(xb) - la);
-}
-
-__device__ __forceinline__ double inv_log_mean_lazy(double xa, double xb, double la, double scale)
-{
-    const double d = xb - xa, s = xa + xb;
-    const double f = d / s;
-    const double u = f * f;
-    if (u < LM_EPS) return (2.0 + u * (C23 + u * (C25 + u * C27))) / s;
-    return (log(xb * scale) - la) / d;
+    const bool ser = d * d < LM_EPS * (s * s);
+    const double x = fdiv(ser ? 1.0 : lb - la, ser ? s : d);
+    const double dx = d * x;
+    const double u = dx * dx;
+    return ser ? 2.0 * x * (1.0 + u * (I1 + u * (I2 + u * I3))) : x;
 }
 
 // Symmetric part of the two-point flux in direction R between nodes a and b
@@ -134,11 +142,12 @@ __device__ __forceinline__ double inv_log_mean_lazy(double xa, double xb, double
 // f^E = f^rho (1/((gamma-1) {{rho/p}}_log) + u_a.u_b/2 + phi_m) +
 //       (p_a u_R,b + p_b u_R,a)/2.   Returns {{rho}}_log for the gravity term.
 template <int R>
-__device__ __forceinline__ double sym_flux(const Node &a, const Node &b, double phi_m,
-                                           double gm1i, double S[5])
+__device__ __forceinline__ double sym_flux(const Node &a, const Node &b, double lra, double lrb,
+                                           double lza, double lzb, double phi_m, double gm1i,
+                                           double S[5])
 {
-    const double rho_ln = log_mean(a.r, b.r, a.lr, b.lr);
-    const double izln = inv_log_mean(a.z, b.z, a.lz, b.lz);
+    const double rho_ln = log_mean(a.r, b.r, lra, lrb);
+    const double izln = inv_log_mean(a.z, b.z, lza, lzb);
     const double uRa = ucomp<R>(a), uRb = ucomp<R>(b);
     const double frho = rho_ln * 0.5 * (uRa + uRb);
     S[0] = frho;
@@ -163,37 +172,57 @@ __device__ __forceinline__ void load_cons(const double *__restrict__ q, int64_t 
     for (int v = 0; v < 5; ++v) c.v[v] = p[v * np];
 }
 
+// Primitive quantities of a conservative state at geopotential phi.
+__device__ __forceinline__ Node primitives(const Cons &c, double phi, double gm1)
+{
+    Node n;
+    n.r = c.v[0];
+    const double ri = fdiv(1.0, n.r);
+    n.u0 = c.v[1] * ri;
+    n.u1 = c.v[2] * ri;
+    n.u2 = c.v[3] * ri;
+    n.p = gm1 * (c.v[4] - 0.5 * (c.v[1] * n.u0 + c.v[2] * n.u1 + c.v[3] * n.u2) - n.r * phi);
+    n.z = fdiv(n.r, n.p);
+    n.zi = n.p * ri;
+    return n;
+}
+
 // Normal face flux F*.n for outward normal n = s e_R at a face node with
-// geopotential phi on both sides (the face nodes of neighbours coincide):
-// s * f_R(q-, q+) - lambda/2 (q+ - q-), lambda = max(|u_R| + c) (Rusanov).
+// geopotential phi on both sides (the face nodes of neighbours coincide, so
+// the gravity term vanishes): s f_R(q-, q+) - lambda/2 (q+ - q-), with
+// lambda = max(|u_R| + c) over both sides (Rusanov), c^2 = gamma p/rho.
+// The own node's primitives come from LDS; logarithms are taken only on the
+// log branch of a log-mean.
 template <int R>
-__device__ __forceinline__ void face_flux(const Cons &qm, const Cons &qp, double phi, double s,
-                                          const StageParams &P, double Fn[5])
+__device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const Cons &qp,
+                                          double phi, double s, const StageParams &P,
+                                          double Fn[5])
 {
     const double g = P.gamma, gm1 = g - 1.0, gm1i = 1.0 / gm1;
-    Node a, b;
+    const Node b = primitives(qp, phi, gm1);
+    double rho_ln, izln;
     {
-        const double r = qm.v[0], ri = 1.0 / r;
-        a.r = r;
-        a.u0 = qm.v[1] * ri;
-        a.u1 = qm.v[2] * ri;
-        a.u2 = qm.v[3] * ri;
-        a.p = gm1 * (qm.v[4] - 0.5 * (qm.v[1] * a.u0 + qm.v[2] * a.u1 + qm.v[3] * a.u2) - r * phi);
-        a.z = r / a.p;
-        a.lr = log(r);
-        a.lz = log(a.z * P.lnz_scale);
+        const double d = b.r - a.r, sm = a.r + b.r;
+        const bool ser = d * d < LM_EPS * (sm * sm);
+        double den = sm;
+        if (!ser) den = log(b.r) - log(a.r);
+        const double x = fdiv(d, den);
+        const double u = x * x;
+        rho_ln = ser ? 0.5 * sm * (1.0 - u * (S1 + u * (S2 + u * S3))) : x;
     }
     {
-        const double r = qp.v[0], ri = 1.0 / r;
-        b.r = r;
-        b.u0 = qp.v[1] * ri;
-        b.u1 = qp.v[2] * ri;
-        b.u2 = qp.v[3] * ri;
-        b.p = gm1 * (qp.v[4] - 0.5 * (qp.v[1] * b.u0 + qp.v[2] * b.u1 + qp.v[3] * b.u2) - r * phi);
-        b.z = r / b.p;
+        const double d = b.z - a.z, sm = a.z + b.z;
+        const bool ser = d * d < LM_EPS * (sm * sm);
+        double num = 1.0, den = sm;
+        if (!ser) {
+            num = log(b.z * P.lnz_scale) - log(a.z * P.lnz_scale);
+            den = d;
+        }
+        const double x = fdiv(num, den);
+        const double dx = d * x;
+        const double u = dx * dx;
+        izln = ser ? 2.0 * x * (1.0 + u * (I1 + u * (I2 + u * I3))) : x;
     }
-    const double rho_ln = log_mean_lazy(a.r, b.r, a.lr);
-    const double izln = inv_log_mean_lazy(a.z, b.z, a.lz, P.lnz_scale);
     const double uRa = ucomp<R>(a), uRb = ucomp<R>(b);
     const double frho = rho_ln * 0.5 * (uRa + uRb);
     double S[5];
@@ -204,14 +233,14 @@ __device__ __forceinline__ void face_flux(const Cons &qm, const Cons &qp, double
     S[1 + R] += 0.5 * (a.p + b.p);
     const double uaub = a.u0 * b.u0 + a.u1 * b.u1 + a.u2 * b.u2;
     S[4] = frho * (izln * gm1i + 0.5 * uaub + phi) + 0.5 * (a.p * uRb + b.p * uRa);
-    double lam = 0.0;
+    double hl = 0.0;
     if (P.surf == 0) {
-        const double la = fabs(uRa) + sqrt(g * a.p / a.r);
-        const double lb = fabs(uRb) + sqrt(g * b.p / b.r);
-        lam = la > lb ? la : lb;
+        const double la = fabs(uRa) + sqrt(g * a.zi);
+        const double lb = fabs(uRb) + sqrt(g * b.zi);
+        hl = 0.5 * (la > lb ? la : lb);
     }
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Fn[v] = s * S[v] - 0.5 * lam * (qp.v[v] - qm.v[v]);
+    for (int v = 0; v < 5; ++v) Fn[v] = s * S[v] - hl * (qp.v[v] - qm.v[v]);
 }
 
 // Node index of position t along the R-line owned by lane m.
@@ -222,6 +251,27 @@ __device__ __forceinline__ int line_node(int m, int t)
     if (R == 0) return t + NQ * m;                              // m = j + NQ k
     if (R == 1) return (m % NQ) + NQ * t + NQ2 * (m / NQ);      // m = i + NQ k
     return m + NQ2 * t;                                         // m = i + NQ j
+}
+
+// Per-node logarithms of one line, computed only when some pair of the line
+// can reach the log branch (the extreme pair maximises |b-a|/(b+a)).
+template <int NQ>
+__device__ __forceinline__ void line_logs(const double x[NQ], double scale, double lx[NQ])
+{
+    double mn = x[0], mx = x[0];
+#pragma unroll
+    for (int t = 1; t < NQ; ++t) {
+        mn = fmin(mn, x[t]);
+        mx = fmax(mx, x[t]);
+    }
+    const double d = mx - mn, s = mx + mn;
+    if (d * d >= LM_EPS_LINE * (s * s)) {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) lx[t] = log(x[t] * scale);
+    } else {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) lx[t] = 0.0;
+    }
 }
 
 // Volume pairs and face terms of one line in direction R; acc receives the
@@ -265,24 +315,30 @@ __device__ __forceinline__ void line_terms(const double (*__restrict__ st)[EPW][
         }
     }
 
+    Node nd[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+        const int n = line_node<NQ, R>(m, t);
+        nd[t].r = st[0][el][n];
+        nd[t].u0 = st[1][el][n];
+        nd[t].u1 = st[2][el][n];
+        nd[t].u2 = st[3][el][n];
+        nd[t].p = st[4][el][n];
+        nd[t].z = st[5][el][n];
+        nd[t].zi = st[6][el][n];
+    }
+
     if (P.mask & TERM_VOL) {
-        Node nd[NQ];
+        double lr[NQ], lz[NQ];
+        {
+            double xr[NQ], xz[NQ];
 #pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-            const int n = line_node<NQ, R>(m, t);
-            nd[t].r = st[0][el][n];
-            nd[t].u0 = st[1][el][n];
-            nd[t].u1 = st[2][el][n];
-            nd[t].u2 = st[3][el][n];
-            nd[t].p = st[4][el][n];
-            nd[t].z = st[5][el][n];
-            nd[t].lr = st[6][el][n];
-            nd[t].lz = st[7][el][n];
-        }
-        double zinv[NQ];
-        if (R == 2) {
-#pragma unroll
-            for (int t = 0; t < NQ; ++t) zinv[t] = nd[t].p / nd[t].r;
+            for (int t = 0; t < NQ; ++t) {
+                xr[t] = nd[t].r;
+                xz[t] = nd[t].z;
+            }
+            line_logs<NQ>(xr, 1.0, lr);
+            line_logs<NQ>(xz, P.lnz_scale, lz);
         }
 #pragma unroll
         for (int a = 0; a < NQ; ++a) {
@@ -290,7 +346,8 @@ __device__ __forceinline__ void line_terms(const double (*__restrict__ st)[EPW][
             for (int b = a + 1; b < NQ; ++b) {
                 const double phi_m = R == 2 ? 0.5 * (phi_k[a] + phi_k[b]) : phi_k[0];
                 double S[5];
-                const double rho_ln = sym_flux<R>(nd[a], nd[b], phi_m, gm1i, S);
+                const double rho_ln =
+                    sym_flux<R>(nd[a], nd[b], lr[a], lr[b], lz[a], lz[b], phi_m, gm1i, S);
                 const double tab = tb.T[a][b], tba = tb.T[b][a];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
@@ -301,8 +358,8 @@ __device__ __forceinline__ void line_terms(const double (*__restrict__ st)[EPW][
                     // gravity term G_ab = rho_hat [[phi]]/2, rho_hat = {{b}} {{rho}}_log / b_a,
                     // b = z/2; partner: G_ba = -G_ab z_a / z_b
                     const double X = 0.25 * rho_ln * (nd[a].z + nd[b].z) * (phi_k[b] - phi_k[a]);
-                    acc[a][3] -= tab * (X * zinv[a]);
-                    acc[b][3] -= tba * (-X * zinv[b]);
+                    acc[a][3] -= tab * (X * nd[a].zi);
+                    acc[b][3] += tba * (X * nd[b].zi);
                 }
             }
         }
@@ -313,8 +370,8 @@ __device__ __forceinline__ void line_terms(const double (*__restrict__ st)[EPW][
         for (int side = 0; side < 2; ++side) {
             const int t = side ? NQ - 1 : 0;
             double Fn[5];
-            face_flux<R>(qm[side], qp[side], R == 2 ? phi_k[t] : phi_k[0], side ? 1.0 : -1.0, P,
-                         Fn);
+            face_flux<R>(nd[t], qm[side], qp[side], R == 2 ? phi_k[t] : phi_k[0],
+                         side ? 1.0 : -1.0, P, Fn);
             const double wi = tb.winv[t];
 #pragma unroll
             for (int v = 0; v < 5; ++v) acc[t][v] -= wi * Fn[v];
@@ -328,11 +385,11 @@ constexpr int block_threads()
     return ((EPW * NQ * NQ + 63) / 64) * 64;
 }
 
-template <int NQ, int EPW>
+template <int NQ, int EPW, int MODE>
 __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const StageParams P)
 {
     constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
-    __shared__ double st[8][EPW][NQ3];
+    __shared__ double st[NST][EPW][NQ3];
     __shared__ double sacc[5][EPW][NQ3];
 
     const OrderTables &tb = c_tab[NQ - 2];
@@ -363,8 +420,8 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
         }
     }
 
-    // phase 0: per-node primitives and logarithms into LDS (lane m = (i, j)
-    // handles the nodes (i, j, 0..N): coalesced loads across lanes)
+    // phase 0: per-node primitives into LDS (lane m = (i, j) handles the
+    // nodes (i, j, 0..N): coalesced loads across lanes)
     if (act) {
         const double gm1 = P.gamma - 1.0;
         bool bad = false;
@@ -373,20 +430,15 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
             const int n = m + NQ2 * k;
             Cons c;
             load_cons(P.q_in, e, NQ3, n, c);
-            const double r = c.v[0], ri = 1.0 / r;
-            const double u0 = c.v[1] * ri, u1 = c.v[2] * ri, u2 = c.v[3] * ri;
-            const double p =
-                gm1 * (c.v[4] - 0.5 * (c.v[1] * u0 + c.v[2] * u1 + c.v[3] * u2) - r * phi_k[k]);
-            const double z = r / p;
-            bad |= !(r > 0.0) || !(p > 0.0);
-            st[0][el][n] = r;
-            st[1][el][n] = u0;
-            st[2][el][n] = u1;
-            st[3][el][n] = u2;
-            st[4][el][n] = p;
-            st[5][el][n] = z;
-            st[6][el][n] = log(r);
-            st[7][el][n] = log(z * P.lnz_scale);
+            const Node nd = primitives(c, phi_k[k], gm1);
+            bad |= !(nd.r > 0.0) || !(nd.p > 0.0);
+            st[0][el][n] = nd.r;
+            st[1][el][n] = nd.u0;
+            st[2][el][n] = nd.u1;
+            st[3][el][n] = nd.u2;
+            st[4][el][n] = nd.p;
+            st[5][el][n] = nd.z;
+            st[6][el][n] = nd.zi;
         }
         if (bad) atomicOr(P.flag, 1);
     }
@@ -442,28 +494,54 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
 #pragma unroll
             for (int v = 0; v < 5; ++v) acc[t][v] = 0.0;
     }
+    // finish: the state arrays never alias (checked on the host), so all
+    // loads of this lane's nodes are issued before the first store
+    const double *__restrict__ qin = P.q_in;
     const bool src = (P.mask & TERM_SRC) != 0;
+    const int64_t base0 = e * 5 * NQ3 + m;
+    double qv[NQ][5];
 #pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-        const int n = m + NQ2 * t;
-        double Rv[5];
+    for (int t = 0; t < NQ; ++t)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Rv[v] = sacc[v][el][n] + P.two_h[2] * acc[t][v];
-        const int64_t base = e * 5 * NQ3 + n;
-        if (src) {
-            const double m1 = P.q_in[base + 1 * NQ3], m2 = P.q_in[base + 2 * NQ3];
-            Rv[1] += P.cor_f * m2;
-            Rv[2] -= P.cor_f * m1;
+        for (int v = 0; v < 5; ++v) qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
+    if (MODE == MODE_RHS) {
+        double *__restrict__ rout = P.r_out;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const int n = m + NQ2 * t;
+            double Rv[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Rv[v] = sacc[v][el][n] + P.two_h[2] * acc[t][v];
+            if (src) {
+                Rv[1] += P.cor_f * qv[t][2];
+                Rv[2] -= P.cor_f * qv[t][1];
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) rout[base0 + v * NQ3 + NQ2 * t] = Rv[v];
         }
-        if (P.mode == MODE_RHS) {
+    } else {
+        double *__restrict__ dqp = P.dq;
+        double *__restrict__ qout = P.q_out;
+        double dv[NQ][5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) P.r_out[base + v * NQ3] = Rv[v];
-        } else {
+        for (int t = 0; t < NQ; ++t)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) dv[t][v] = dqp[base0 + v * NQ3 + NQ2 * t];
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const int n = m + NQ2 * t;
+            double Rv[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Rv[v] = sacc[v][el][n] + P.two_h[2] * acc[t][v];
+            if (src) {
+                Rv[1] += P.cor_f * qv[t][2];
+                Rv[2] -= P.cor_f * qv[t][1];
+            }
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double d = P.A * P.dq[base + v * NQ3] + P.dt * Rv[v];
-                P.dq[base + v * NQ3] = d;
-                P.q_out[base + v * NQ3] = P.q_in[base + v * NQ3] + P.B * d;
+                const double d = P.A * dv[t][v] + P.dt * Rv[v];
+                dqp[base0 + v * NQ3 + NQ2 * t] = d;
+                qout[base0 + v * NQ3 + NQ2 * t] = qv[t][v] + P.B * d;
             }
         }
     }
@@ -630,6 +708,21 @@ __global__ void __launch_bounds__(RED_THREADS)
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Plain streaming copy, two doubles per lane per iteration.
+__global__ void __launch_bounds__(256) copy_kernel(const double2 *__restrict__ src,
+                                                   double2 *__restrict__ dst, int64_t n2)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
+        dst[i] = src[i];
+}
+
+__global__ void copy_tail_kernel(const double *__restrict__ src, double *__restrict__ dst,
+                                 int64_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && (n & 1)) dst[n - 1] = src[n - 1];
 }
 
 }  // namespace esdg

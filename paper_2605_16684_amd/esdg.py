@@ -61,6 +61,7 @@ SIGNATURES = {
     "esdg_mesh_info": (C.c_int, [C.c_void_p, _i64p, _i64p, _i64p, _i64p]),
     "esdg_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "esdg_set_epw": (C.c_int, [C.c_void_p, C.c_int32]),
+    "esdg_get_epw": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "esdg_node_coords": (C.c_int, [C.c_void_p, C.c_void_p]),
     "esdg_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
     "esdg_rhs_terms": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
@@ -73,6 +74,7 @@ SIGNATURES = {
     "esdg_last_error": (C.c_char_p, []),
     "esdg_version": (C.c_char_p, []),
     "esdg_lgl_tables": (C.c_int, [C.c_int32, _dp, _dp, _dp]),
+    "esdg_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
 }
 
 
@@ -109,6 +111,15 @@ def lgl_tables(N: int):
     _check(lib.esdg_lgl_tables(N, x.ctypes.data_as(_dp), w.ctypes.data_as(_dp),
                                D.ctypes.data_as(_dp)))
     return x, w, D.reshape(N + 1, N + 1)
+
+
+def copy(src, dst):
+    """dst <- src (same-size float64 CUDA tensors) with the library's copy kernel."""
+    torch = _torch()
+    assert src.dtype == dst.dtype == torch.float64 and src.numel() == dst.numel()
+    assert src.is_contiguous() and dst.is_contiguous()
+    _check(lib.esdg_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), src.numel(),
+                         C.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
 
 def _torch():
@@ -181,6 +192,12 @@ class Mesh:
 
     def set_epw(self, epw: int):
         _check(lib.esdg_set_epw(self._h, epw))
+
+    @property
+    def epw(self) -> int:
+        v = C.c_int32()
+        _check(lib.esdg_get_epw(self._h, C.byref(v)))
+        return v.value
 
     def coords(self):
         torch = _torch()

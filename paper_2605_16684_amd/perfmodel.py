@@ -1,0 +1,70 @@
+"""Algorithmic work and traffic of the fused ES-DGSEM stage, and the MI355X
+roofline it is measured against.
+
+Algorithmic counts come from the formulas the kernels evaluate (each +, -,
+*, /, sqrt and log counts one flop, an FMA two), not from executed
+instructions:
+
+  pair (x or y line, series branch of both log-means)   73 flops
+      two log-means 11 + 11, f^rho 3, momentum 12, u_a.u_b 5,
+      energy 11, accumulation into both nodes 20
+  pair on a z line (adds the gravity term and its partner scaling) 87
+  per-node precompute (primitives, rho/p, two logs, 1/z)            19
+  face node (both states' primitives, log-means, flux, Rusanov
+      dissipation, lift)                                             126
+  per-node finish (phase sums, Coriolis, LSRK update)                 55
+
+Pairs per node: 3N/2 (Nq(Nq-1)/2 pairs per line, Nq^2 lines per direction,
+three directions, Nq^3 nodes).  Face nodes per node: 6/Nq.
+
+Algorithmic HBM bytes per node and stage (FP64): read q and dq, write q_out
+and dq (4 x 40 B) plus the neighbours' face traces (6 faces of Nq^2 nodes of
+40 B per element: 240/Nq B per node).  One RHS evaluation without the update
+moves 40 + 40 + 240/Nq B per node.
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
+FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
+
+PAIR_XY, PAIR_Z, PRECOMP, FACE_NODE, FINISH_STAGE, FINISH_RHS = 73, 87, 19, 126, 55, 20
+
+
+def pairs_per_node(N: int) -> float:
+    return 1.5 * N
+
+
+def flops_per_node(N: int, stage: bool = True) -> float:
+    Nq = N + 1
+    pair = (2 * PAIR_XY + PAIR_Z) / 3.0
+    return (pair * pairs_per_node(N) + FACE_NODE * 6.0 / Nq + PRECOMP
+            + (FINISH_STAGE if stage else FINISH_RHS))
+
+
+def bytes_per_node(N: int, stage: bool = True, word: int = 8) -> float:
+    Nq = N + 1
+    own = (4 if stage else 2) * 5 * word
+    return own + 6.0 * 5 * word / Nq
+
+
+def ridge_fp64() -> float:
+    return FP64_VECTOR_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+
+
+_SRC_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources: hardware counters taken for an older kernel
+    are not reported for the current one."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(_SRC_DIR)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(_SRC_DIR, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
