@@ -234,7 +234,7 @@ int default_epw(int N)
     case 1: return 16;
     case 2: return 7;
     case 3: return 4;
-    case 4: return 2;
+    case 4: return 5;
     case 5: return 3;
     case 6: return 2;
     case 7: return 1;

@@ -75,63 +75,69 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * per + (x < rem ? x : rem) + i;
 }
 
-// Per-node quantities staged in LDS (one double each): density, velocity,
-// pressure, z = rho/p (= 2b) and its reciprocal p/rho.
-constexpr int NST = 7;
+// Per-node quantities of one line, held in registers: density, half
+// velocity, half pressure, z = rho/p (= 2b) and p/rho.  Halved velocity and
+// pressure turn every arithmetic mean of the two-point flux into one add.
 struct Node {
-    double r, u0, u1, u2, p, z, zi;
+    double r, h0, h1, h2, hp, z, zi;
 };
 
 template <int R>
-__device__ __forceinline__ double ucomp(const Node &n)
+__device__ __forceinline__ double hcomp(const Node &n)
 {
-    return R == 0 ? n.u0 : (R == 1 ? n.u1 : n.u2);
+    return R == 0 ? n.h0 : (R == 1 ? n.h1 : n.h2);
 }
 
-// a/b by Newton-Raphson refinement of the hardware reciprocal estimate
-// (two Newton steps on 1/b, then one residual correction of the quotient;
-// Markstein's scheme).  For the normal, finite operands met here it agrees
-// with the IEEE quotient; it skips the range scaling and special-value
-// fix-up of the full division sequence.
-__device__ __forceinline__ double fdiv(double a, double b)
+// 1/b by two Newton-Raphson steps on the hardware reciprocal estimate.
+__device__ __forceinline__ double frcp(double b)
 {
     double r = __builtin_amdgcn_rcp(b);
     double e = fma(-b, r, 1.0);
     r = fma(r, e, r);
     e = fma(-b, r, 1.0);
-    r = fma(r, e, r);
-    const double q = a * r;
-    const double rem = fma(-b, q, a);
-    return fma(rem, r, q);
+    return fma(r, e, r);
 }
 
-// Log-mean branch rule: u = ((b-a)/(b+a))^2 < 1e-4 takes the series.
-constexpr double LM_EPS = 1e-4;
+// a/b: the refined reciprocal and one residual correction of the quotient
+// (Markstein's scheme).  For the normal, finite operands met here it agrees
+// with the IEEE quotient; it skips the range scaling and special-value
+// fix-up of the full division sequence.
+__device__ __forceinline__ double fdiv(double a, double b)
+{
+    const double r = frcp(b);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+}
+
+// Log-mean branch rule: u = ((b-a)/(b+a))^2 < 1e-4 takes the series, i.e.
+// |b-a| < 1e-2 (b+a).
+constexpr double LM_SQRT_EPS = 1e-2;
 // The per-line test that decides whether a line needs per-node logarithms
 // is slightly tighter, so that a line declared log-free never has a pair
 // whose own test selects the log branch.
-constexpr double LM_EPS_LINE = 0.999e-4;
+constexpr double LM_SQRT_EPS_LINE = 0.9999e-2;
 // {{x}}_log = (a+b)/2 * f/atanh(f), f/atanh(f) = 1 - u/3 - 4u^2/45 - 44u^3/945 - ...
 constexpr double S1 = 1.0 / 3.0, S2 = 4.0 / 45.0, S3 = 44.0 / 945.0;
 // 1/{{x}}_log = 2/(a+b) * atanh(f)/f,  atanh(f)/f = 1 + u/3 + u^2/5 + u^3/7 + ...
 constexpr double I1 = 1.0 / 3.0, I2 = 1.0 / 5.0, I3 = 1.0 / 7.0;
 
-// {{x}}_log with one division: series x = d/s, else x = d/(ln b - ln a).
+// {{x}}_log with one reciprocal: series x = d/s, else x = d/(ln b - ln a).
 __device__ __forceinline__ double log_mean(double xa, double xb, double la, double lb)
 {
     const double d = xb - xa, s = xa + xb;
-    const bool ser = d * d < LM_EPS * (s * s);
-    const double x = fdiv(d, ser ? s : lb - la);
+    const bool ser = fabs(d) < LM_SQRT_EPS * s;
+    const double x = d * frcp(ser ? s : lb - la);
     const double u = x * x;
     return ser ? 0.5 * s * (1.0 - u * (S1 + u * (S2 + u * S3))) : x;
 }
 
-// 1/{{x}}_log with one division: series x = 1/s, else x = (ln b - ln a)/d.
+// 1/{{x}}_log with one reciprocal: series x = 1/s, else x = (ln b - ln a)/d.
 __device__ __forceinline__ double inv_log_mean(double xa, double xb, double la, double lb)
 {
     const double d = xb - xa, s = xa + xb;
-    const bool ser = d * d < LM_EPS * (s * s);
-    const double x = fdiv(ser ? 1.0 : lb - la, ser ? s : d);
+    const bool ser = fabs(d) < LM_SQRT_EPS * s;
+    const double r = frcp(ser ? s : d);
+    const double x = ser ? r : (lb - la) * r;
     const double dx = d * x;
     const double u = dx * dx;
     return ser ? 2.0 * x * (1.0 + u * (I1 + u * (I2 + u * I3))) : x;
@@ -148,15 +154,16 @@ __device__ __forceinline__ double sym_flux(const Node &a, const Node &b, double 
 {
     const double rho_ln = log_mean(a.r, b.r, lra, lrb);
     const double izln = inv_log_mean(a.z, b.z, lza, lzb);
-    const double uRa = ucomp<R>(a), uRb = ucomp<R>(b);
-    const double frho = rho_ln * 0.5 * (uRa + uRb);
+    const double hRa = hcomp<R>(a), hRb = hcomp<R>(b);
+    const double frho = rho_ln * (hRa + hRb);
     S[0] = frho;
-    S[1] = frho * 0.5 * (a.u0 + b.u0);
-    S[2] = frho * 0.5 * (a.u1 + b.u1);
-    S[3] = frho * 0.5 * (a.u2 + b.u2);
-    S[1 + R] += 0.5 * (a.p + b.p);
-    const double uaub = a.u0 * b.u0 + a.u1 * b.u1 + a.u2 * b.u2;
-    S[4] = frho * (izln * gm1i + 0.5 * uaub + phi_m) + 0.5 * (a.p * uRb + b.p * uRa);
+    S[1] = frho * (a.h0 + b.h0);
+    S[2] = frho * (a.h1 + b.h1);
+    S[3] = frho * (a.h2 + b.h2);
+    S[1 + R] += a.hp + b.hp;
+    const double hh = a.h0 * b.h0 + a.h1 * b.h1 + a.h2 * b.h2;  // u_a.u_b / 4
+    const double cross = a.hp * hRb + b.hp * hRa;                 // (p_a u_b + p_b u_a) / 4
+    S[4] = frho * (izln * gm1i + 2.0 * hh + phi_m) + 2.0 * cross;
     return rho_ln;
 }
 
@@ -177,13 +184,15 @@ __device__ __forceinline__ Node primitives(const Cons &c, double phi, double gm1
 {
     Node n;
     n.r = c.v[0];
-    const double ri = fdiv(1.0, n.r);
-    n.u0 = c.v[1] * ri;
-    n.u1 = c.v[2] * ri;
-    n.u2 = c.v[3] * ri;
-    n.p = gm1 * (c.v[4] - 0.5 * (c.v[1] * n.u0 + c.v[2] * n.u1 + c.v[3] * n.u2) - n.r * phi);
-    n.z = fdiv(n.r, n.p);
-    n.zi = n.p * ri;
+    const double ri = frcp(n.r);
+    const double hri = 0.5 * ri;
+    n.h0 = c.v[1] * hri;
+    n.h1 = c.v[2] * hri;
+    n.h2 = c.v[3] * hri;
+    const double p = gm1 * (c.v[4] - (c.v[1] * n.h0 + c.v[2] * n.h1 + c.v[3] * n.h2) - n.r * phi);
+    n.hp = 0.5 * p;
+    n.z = fdiv(n.r, p);
+    n.zi = p * ri;
     return n;
 }
 
@@ -191,8 +200,7 @@ __device__ __forceinline__ Node primitives(const Cons &c, double phi, double gm1
 // geopotential phi on both sides (the face nodes of neighbours coincide, so
 // the gravity term vanishes): s f_R(q-, q+) - lambda/2 (q+ - q-), with
 // lambda = max(|u_R| + c) over both sides (Rusanov), c^2 = gamma p/rho.
-// The own node's primitives come from LDS; logarithms are taken only on the
-// log branch of a log-mean.
+// Logarithms are taken only on the log branch of a log-mean.
 template <int R>
 __device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const Cons &qp,
                                           double phi, double s, const StageParams &P,
@@ -203,7 +211,7 @@ __device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const C
     double rho_ln, izln;
     {
         const double d = b.r - a.r, sm = a.r + b.r;
-        const bool ser = d * d < LM_EPS * (sm * sm);
+        const bool ser = fabs(d) < LM_SQRT_EPS * sm;
         double den = sm;
         if (!ser) den = log(b.r) - log(a.r);
         const double x = fdiv(d, den);
@@ -212,7 +220,7 @@ __device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const C
     }
     {
         const double d = b.z - a.z, sm = a.z + b.z;
-        const bool ser = d * d < LM_EPS * (sm * sm);
+        const bool ser = fabs(d) < LM_SQRT_EPS * sm;
         double num = 1.0, den = sm;
         if (!ser) {
             num = log(b.z * P.lnz_scale) - log(a.z * P.lnz_scale);
@@ -223,20 +231,21 @@ __device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const C
         const double u = dx * dx;
         izln = ser ? 2.0 * x * (1.0 + u * (I1 + u * (I2 + u * I3))) : x;
     }
-    const double uRa = ucomp<R>(a), uRb = ucomp<R>(b);
-    const double frho = rho_ln * 0.5 * (uRa + uRb);
+    const double hRa = hcomp<R>(a), hRb = hcomp<R>(b);
+    const double frho = rho_ln * (hRa + hRb);
     double S[5];
     S[0] = frho;
-    S[1] = frho * 0.5 * (a.u0 + b.u0);
-    S[2] = frho * 0.5 * (a.u1 + b.u1);
-    S[3] = frho * 0.5 * (a.u2 + b.u2);
-    S[1 + R] += 0.5 * (a.p + b.p);
-    const double uaub = a.u0 * b.u0 + a.u1 * b.u1 + a.u2 * b.u2;
-    S[4] = frho * (izln * gm1i + 0.5 * uaub + phi) + 0.5 * (a.p * uRb + b.p * uRa);
+    S[1] = frho * (a.h0 + b.h0);
+    S[2] = frho * (a.h1 + b.h1);
+    S[3] = frho * (a.h2 + b.h2);
+    S[1 + R] += a.hp + b.hp;
+    const double hh = a.h0 * b.h0 + a.h1 * b.h1 + a.h2 * b.h2;
+    const double cross = a.hp * hRb + b.hp * hRa;
+    S[4] = frho * (izln * gm1i + 2.0 * hh + phi) + 2.0 * cross;
     double hl = 0.0;
     if (P.surf == 0) {
-        const double la = fabs(uRa) + sqrt(g * a.zi);
-        const double lb = fabs(uRb) + sqrt(g * b.zi);
+        const double la = 2.0 * fabs(hRa) + sqrt(g * a.zi);
+        const double lb = 2.0 * fabs(hRb) + sqrt(g * b.zi);
         hl = 0.5 * (la > lb ? la : lb);
     }
 #pragma unroll
@@ -264,8 +273,7 @@ __device__ __forceinline__ void line_logs(const double x[NQ], double scale, doub
         mn = fmin(mn, x[t]);
         mx = fmax(mx, x[t]);
     }
-    const double d = mx - mn, s = mx + mn;
-    if (d * d >= LM_EPS_LINE * (s * s)) {
+    if (mx - mn >= LM_SQRT_EPS_LINE * (mx + mn)) {
 #pragma unroll
         for (int t = 0; t < NQ; ++t) lx[t] = log(x[t] * scale);
     } else {
@@ -275,58 +283,50 @@ __device__ __forceinline__ void line_logs(const double x[NQ], double scale, doub
 }
 
 // Volume pairs and face terms of one line in direction R; acc receives the
-// unscaled sums (the caller multiplies by 2/h_R).
-template <int NQ, int EPW, int R>
-__device__ __forceinline__ void line_terms(const double (*__restrict__ st)[EPW][NQ * NQ * NQ],
-                                           const StageParams &P, const OrderTables &tb, int el,
-                                           int m, int64_t e, const int ec[3],
-                                           const double phi_k[NQ], double acc[NQ][5])
+// unscaled sums (the caller multiplies by 2/h_R); qv receives the line's
+// conservative states (the z phase reuses them for the update).
+template <int NQ, int R>
+__device__ __forceinline__ void line_terms(const StageParams &P, const OrderTables &tb, int m,
+                                           int64_t e, const int ec[3], const double phi_k[NQ],
+                                           double acc[NQ][5], double qv[NQ][5])
 {
     constexpr int NQ3 = NQ * NQ * NQ;
-    const double gm1i = 1.0 / (P.gamma - 1.0);
+    const double gm1 = P.gamma - 1.0, gm1i = 1.0 / gm1;
+    const double *__restrict__ qin = P.q_in;
 #pragma unroll
     for (int a = 0; a < NQ; ++a)
 #pragma unroll
         for (int v = 0; v < 5; ++v) acc[a][v] = 0.0;
 
-    // issue the face-neighbour loads first: their latency hides behind the pairs
-    Cons qm[2], qp[2];
+    // the line's own states, then the face neighbours' (their latency hides
+    // behind the pair loop)
+    Cons qc[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) load_cons(qin, e, NQ3, line_node<NQ, R>(m, t), qc[t]);
+    Cons qp[2];
     const bool faces = (P.mask & TERM_FACE) != 0;
     if (faces) {
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-            const int t = side ? NQ - 1 : 0;
-            const int n = line_node<NQ, R>(m, t);
-            load_cons(P.q_in, e, NQ3, n, qm[side]);
             int nb = ec[R] + (side ? 1 : -1);
             const bool wall = (nb < 0 || nb >= P.K[R]) && !P.periodic[R];
-            if (wall) {
-                qp[side] = qm[side];
-                qp[side].v[1 + R] = -qp[side].v[1 + R];
-            } else {
+            if (!wall) {
                 if (nb < 0) nb += P.K[R];
                 if (nb >= P.K[R]) nb -= P.K[R];
                 int cc[3] = {ec[0], ec[1], ec[2]};
                 cc[R] = nb;
                 const int64_t en = cc[0] + (int64_t)P.K[0] * (cc[1] + (int64_t)P.K[1] * cc[2]);
-                const int nn = line_node<NQ, R>(m, side ? 0 : NQ - 1);
-                load_cons(P.q_in, en, NQ3, nn, qp[side]);
+                load_cons(qin, en, NQ3, line_node<NQ, R>(m, side ? 0 : NQ - 1), qp[side]);
+            } else {
+                qp[side] = qc[side ? NQ - 1 : 0];
+                qp[side].v[1 + R] = -qp[side].v[1 + R];
             }
         }
     }
 
     Node nd[NQ];
 #pragma unroll
-    for (int t = 0; t < NQ; ++t) {
-        const int n = line_node<NQ, R>(m, t);
-        nd[t].r = st[0][el][n];
-        nd[t].u0 = st[1][el][n];
-        nd[t].u1 = st[2][el][n];
-        nd[t].u2 = st[3][el][n];
-        nd[t].p = st[4][el][n];
-        nd[t].z = st[5][el][n];
-        nd[t].zi = st[6][el][n];
-    }
+    for (int t = 0; t < NQ; ++t) nd[t] = primitives(qc[t], R == 2 ? phi_k[t] : phi_k[0], gm1);
 
     if (P.mask & TERM_VOL) {
         double lr[NQ], lz[NQ];
@@ -370,13 +370,17 @@ __device__ __forceinline__ void line_terms(const double (*__restrict__ st)[EPW][
         for (int side = 0; side < 2; ++side) {
             const int t = side ? NQ - 1 : 0;
             double Fn[5];
-            face_flux<R>(nd[t], qm[side], qp[side], R == 2 ? phi_k[t] : phi_k[0],
+            face_flux<R>(nd[t], qc[t], qp[side], R == 2 ? phi_k[t] : phi_k[0],
                          side ? 1.0 : -1.0, P, Fn);
             const double wi = tb.winv[t];
 #pragma unroll
             for (int v = 0; v < 5; ++v) acc[t][v] -= wi * Fn[v];
         }
     }
+#pragma unroll
+    for (int t = 0; t < NQ; ++t)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qv[t][v] = qc[t].v[v];
 }
 
 template <int NQ, int EPW>
@@ -385,11 +389,12 @@ constexpr int block_threads()
     return ((EPW * NQ * NQ + 63) / 64) * 64;
 }
 
+// One workgroup handles EPW elements; lane (el, m) owns line m of element el
+// in each of the three phases.  LDS holds only the cross-phase accumulator.
 template <int NQ, int EPW, int MODE>
 __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const StageParams P)
 {
     constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
-    __shared__ double st[NST][EPW][NQ3];
     __shared__ double sacc[5][EPW][NQ3];
 
     const OrderTables &tb = c_tab[NQ - 2];
@@ -420,51 +425,27 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
         }
     }
 
-    // phase 0: per-node primitives into LDS (lane m = (i, j) handles the
-    // nodes (i, j, 0..N): coalesced loads across lanes)
-    if (act) {
-        const double gm1 = P.gamma - 1.0;
-        bool bad = false;
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            const int n = m + NQ2 * k;
-            Cons c;
-            load_cons(P.q_in, e, NQ3, n, c);
-            const Node nd = primitives(c, phi_k[k], gm1);
-            bad |= !(nd.r > 0.0) || !(nd.p > 0.0);
-            st[0][el][n] = nd.r;
-            st[1][el][n] = nd.u0;
-            st[2][el][n] = nd.u1;
-            st[3][el][n] = nd.u2;
-            st[4][el][n] = nd.p;
-            st[5][el][n] = nd.z;
-            st[6][el][n] = nd.zi;
-        }
-        if (bad) atomicOr(P.flag, 1);
-    }
-    __syncthreads();
-
-    double acc[NQ][5];
+    double acc[NQ][5], qv[NQ][5];
     const bool vol_or_face = (P.mask & (TERM_VOL | TERM_FACE)) != 0;
 
     // x phase: lane m = (j, k)
-    if (act && vol_or_face) {
-        double phl[NQ];
+    if (act) {
+        if (vol_or_face) {
+            double phl[NQ];
 #pragma unroll
-        for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
-        line_terms<NQ, EPW, 0>(st, P, tb, el, m, e, ec, phl, acc);
+            for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
+            line_terms<NQ, 0>(P, tb, m, e, ec, phl, acc, qv);
+        } else {
+#pragma unroll
+            for (int t = 0; t < NQ; ++t)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[t][v] = 0.0;
+        }
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             const int n = line_node<NQ, 0>(m, t);
 #pragma unroll
             for (int v = 0; v < 5; ++v) sacc[v][el][n] = P.two_h[0] * acc[t][v];
-        }
-    } else if (act) {
-#pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-            const int n = line_node<NQ, 0>(m, t);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) sacc[v][el][n] = 0.0;
         }
     }
     __syncthreads();
@@ -474,7 +455,7 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
         double phl[NQ];
 #pragma unroll
         for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
-        line_terms<NQ, EPW, 1>(st, P, tb, el, m, e, ec, phl, acc);
+        line_terms<NQ, 1>(P, tb, m, e, ec, phl, acc, qv);
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             const int n = line_node<NQ, 1>(m, t);
@@ -486,24 +467,25 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
 
     // z phase: lane m = (i, j) owns the nodes (i, j, 0..N) and finishes them
     if (!act) return;
-    if (vol_or_face) {
-        line_terms<NQ, EPW, 2>(st, P, tb, el, m, e, ec, phi_k, acc);
-    } else {
-#pragma unroll
-        for (int t = 0; t < NQ; ++t)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) acc[t][v] = 0.0;
-    }
-    // finish: the state arrays never alias (checked on the host), so all
-    // loads of this lane's nodes are issued before the first store
-    const double *__restrict__ qin = P.q_in;
     const bool src = (P.mask & TERM_SRC) != 0;
+    if (vol_or_face) {
+        line_terms<NQ, 2>(P, tb, m, e, ec, phi_k, acc, qv);
+    } else {
+        const double *__restrict__ qin = P.q_in;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            Cons c;
+            load_cons(qin, e, NQ3, m + NQ2 * t, c);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                acc[t][v] = 0.0;
+                qv[t][v] = c.v[v];
+            }
+        }
+    }
+    // finish: the state arrays never overlap (checked on the host), so the
+    // loads of dq are issued together before the first store
     const int64_t base0 = e * 5 * NQ3 + m;
-    double qv[NQ][5];
-#pragma unroll
-    for (int t = 0; t < NQ; ++t)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
     if (MODE == MODE_RHS) {
         double *__restrict__ rout = P.r_out;
 #pragma unroll
@@ -544,6 +526,17 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
                 qout[base0 + v * NQ3 + NQ2 * t] = qv[t][v] + P.B * d;
             }
         }
+    }
+    if (P.flag) {
+        bool bad = false;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const double r = qv[t][0];
+            const double kin = qv[t][1] * qv[t][1] + qv[t][2] * qv[t][2] + qv[t][3] * qv[t][3];
+            const double eint = qv[t][4] - 0.5 * kin / r - r * phi_k[t];
+            bad |= !(r > 0.0) || !(eint > 0.0);
+        }
+        if (bad) atomicOr(P.flag, 1);
     }
 }
 
