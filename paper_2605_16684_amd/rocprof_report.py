@@ -1,0 +1,138 @@
+"""Summaries of rocprofv3 result databases (host-only tool).
+
+  python -m paper_2605_16684_amd.rocprof_report stats DB --cmd "..." [--out FILE]
+      kernel table (calls, average and total duration) from a
+      `rocprofv3 --kernel-trace --stats` run;
+  python -m paper_2605_16684_amd.rocprof_report traffic FETCH_DB WRITE_DB
+          --workload NAME --cmd-fetch "..." --cmd-write "..." [--out FILE] [--json FILE]
+      HBM bytes per launch of each stage kernel from `--pmc FETCH_SIZE` and
+      `--pmc WRITE_SIZE` runs, each scaled by what the same counter reads for
+      the library's copy kernel of known size (1 GiB read + 1 GiB written,
+      run by `bench.py --calib-copy`).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import os
+import sqlite3
+import sys
+
+COPY_BYTES = 1 << 30
+
+
+def _rows(db, sql, args=()):
+    con = sqlite3.connect(db)
+    try:
+        return list(con.execute(sql, args))
+    finally:
+        con.close()
+
+
+def kernel_stats(db):
+    return _rows(db, "select name, total_calls, total_duration, average from top_kernels "
+                     "order by total_duration desc")
+
+
+def counter_by_kernel(db, counter):
+    out = collections.defaultdict(list)
+    for name, val in _rows(db, "select kernel_name, value from counters_collection "
+                               "where counter_name = ? order by dispatch_id", (counter,)):
+        out[name].append(val)
+    return out
+
+
+def _copy_factor(per_kernel):
+    vals = [v for k, vs in per_kernel.items() if "copy_kernel" in k for v in vs]
+    if not vals:
+        raise SystemExit("no esdg::copy_kernel dispatch in the counter run (use --calib-copy)")
+    kib = sum(vals) / len(vals)
+    return COPY_BYTES / (kib * 1024.0), kib
+
+
+def cmd_stats(a):
+    rows = kernel_stats(a.db)
+    lines = [f"# rocprofv3 kernel trace: {a.title}", "", "Command:", "", "```", a.cmd, "```", "",
+             "| kernel | calls | avg (us) | total (us) |", "|---|---:|---:|---:|"]
+    for name, calls, total, avg in rows:
+        lines.append(f"| `{name[:110]}` | {calls} | {avg:.2f} | {total:.1f} |")
+    txt = "\n".join(lines) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
+    print(txt)
+
+
+def cmd_traffic(a):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_2605_16684_amd import perfmodel
+    fetch = counter_by_kernel(a.fetch_db, "FETCH_SIZE")
+    write = counter_by_kernel(a.write_db, "WRITE_SIZE")
+    ff, fkib = _copy_factor(fetch)
+    wf, wkib = _copy_factor(write)
+    lines = [f"# HBM traffic per launch: {a.workload}", "",
+             "Commands (FETCH_SIZE pass, then WRITE_SIZE pass):", "", "```", a.cmd_fetch,
+             a.cmd_write, "```", "",
+             f"Calibration with the library copy kernel (1 GiB read + 1 GiB written): "
+             f"FETCH_SIZE reads {fkib:.0f} KiB -> factor {ff:.4f}; "
+             f"WRITE_SIZE reads {wkib:.0f} KiB -> factor {wf:.4f}.", "",
+             "| kernel | launches | FETCH (MB, scaled) | WRITE (MB, scaled) | total (MB) |",
+             "|---|---:|---:|---:|---:|"]
+    rec = {}
+    for name in sorted(fetch):
+        if "stage_fp" not in name or name not in write:
+            continue
+        fv, wv = fetch[name], write[name]
+        n = min(len(fv), len(wv))
+        fb = sum(fv[:n]) / n * 1024.0 * ff
+        wb = sum(wv[:n]) / n * 1024.0 * wf
+        lines.append(f"| `{name}` | {n} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} |")
+        mode = "rhs" if name.rstrip(")").split("(")[0].rstrip(">").endswith(" 0") else "stage"
+        rec[name] = {"mode": mode, "fetch_bytes": fb, "write_bytes": wb,
+                     "bytes_per_launch": fb + wb}
+    txt = "\n".join(lines) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
+    print(txt)
+    if a.json:
+        data = {}
+        if os.path.exists(a.json):
+            with open(a.json) as f:
+                data = json.load(f)
+        ent = data.setdefault(a.workload, {})
+        for name, r in rec.items():
+            key = "stage_fp64" if (r["mode"] == "stage" and "stage_fp64" in name) else name
+            r = dict(r, kernel=name, kernel_hash=perfmodel.kernel_source_hash(),
+                     fetch_factor=ff, write_factor=wf)
+            ent[key] = r
+        with open(a.json, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--cmd", required=True)
+    s.add_argument("--title", default="")
+    s.add_argument("--out")
+    s.set_defaults(fn=cmd_stats)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_db")
+    t.add_argument("write_db")
+    t.add_argument("--workload", required=True)
+    t.add_argument("--cmd-fetch", required=True)
+    t.add_argument("--cmd-write", required=True)
+    t.add_argument("--out")
+    t.add_argument("--json")
+    t.set_defaults(fn=cmd_traffic)
+    a = ap.parse_args(argv)
+    a.fn(a)
+
+
+if __name__ == "__main__":
+    main()
