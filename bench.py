@@ -68,6 +68,91 @@ def cpu_baseline(wl, seconds, seed=1):
                       f"{wl.name}, {el:.1f} s"}
 
 
+def precision_block(esdg, W, torch, steps=100, workload="c3"):
+    """FP64 vs FP32-mixed on the same workload: RHS launch and LSRK step
+    throughput, RHS difference (the FP64 path matches the oracle to 1e-16 of
+    the gross term scale, see tests), state difference after `steps` steps,
+    and conservation / entropy drift."""
+    import numpy as np
+    wl = W.WORKLOADS[workload]
+    spec = wl.mesh
+    m64 = esdg.Mesh(spec)
+    xyz = m64.coords().cpu().numpy()
+    q0 = W.make_state(wl.kind, xyz, spec, seed=1)
+    rr, pr = W.reference_state(xyz, spec, wl.kind)
+    del xyz
+    rr_t = torch.from_numpy(np.ascontiguousarray(rr)).cuda()
+    pr_t = torch.from_numpy(np.ascontiguousarray(pr)).cuda()
+    del rr, pr
+    m32 = esdg.Mesh(spec, precision=esdg.FP32_MIXED, ref_rho=rr_t, ref_p=pr_t)
+    qd = torch.from_numpy(q0).cuda()
+    del q0
+    nn = m64.n_nodes
+    out = {"workload": wl.name, "nodes": nn, "N": spec.N}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+
+    def t_rhs(m, reps=10):
+        r = torch.empty_like(qd)
+        for _ in range(2):
+            m.rhs(qd, r)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            m.rhs(qd, r)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) * 1e-3 / reps, r
+
+    def run(m, dt, n):
+        q = qd.clone()
+        dq = torch.zeros_like(q)
+        e0 = m.entropy(q)
+        m.lsrk_run(q, dq, dt, 2)  # warm-up and graph capture on a copy
+        q.copy_(qd)
+        dq.zero_()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        m.lsrk_run(q, dq, dt, n)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        e1 = m.entropy(q)
+        return ev0.elapsed_time(ev1) * 1e-3 / n, q, e0, e1
+
+    t64, r64 = t_rhs(m64)
+    t32, r32 = t_rhs(m32)
+    d = (r32 - r64).double()
+    net = [float(torch.linalg.norm(d[:, v]) / torch.linalg.norm(r64[:, v])) for v in range(5)]
+    del r32, d
+    dt = m64.cfl_dt(qd, wl.cfl)
+    s64, q64, a0, a1 = run(m64, dt, steps)
+    s32, q32, b0, b1 = run(m32, dt, steps)
+    dq = q32 - q64
+    state = [float(torch.linalg.norm(dq[:, 0]) / torch.linalg.norm(q64[:, 0])),
+             float(torch.linalg.norm(dq[:, 1:4]) / torch.linalg.norm(q64[:, 1:4])),
+             float(torch.linalg.norm(dq[:, 4]) / torch.linalg.norm(q64[:, 4]))]
+    out.update({
+        "fp64": {"rhs_ms": t64 * 1e3, "rhs_dof_per_s": nn / t64, "step_ms": s64 * 1e3,
+                 "dof_rhs_per_s": nn * 5 / s64,
+                 "mass_drift": abs(a1[1] - a0[1]) / abs(a0[1]),
+                 "energy_drift": abs(a1[2] - a0[2]) / abs(a0[2]),
+                 "entropy_change": (a1[0] - a0[0]) / abs(a0[0])},
+        "fp32_mixed": {"rhs_ms": t32 * 1e3, "rhs_dof_per_s": nn / t32, "step_ms": s32 * 1e3,
+                       "dof_rhs_per_s": nn * 5 / s32,
+                       "mass_drift": abs(b1[1] - b0[1]) / abs(b0[1]),
+                       "energy_drift": abs(b1[2] - b0[2]) / abs(b0[2]),
+                       "entropy_change": (b1[0] - b0[0]) / abs(b0[0])},
+        "rhs_speedup": t64 / t32, "step_speedup": s64 / s32,
+        "rhs_rel_l2_vs_fp64_per_var": net,
+        "steps": steps, "dt": dt,
+        "state_rel_l2_vs_fp64_after_steps": {"rho": state[0], "momentum": state[1],
+                                             "energy": state[2]},
+    })
+    m64.close()
+    m32.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +162,9 @@ def main():
     ap.add_argument("--epw", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP64 vs FP32-mixed comparison")
+    ap.add_argument("--precision-workload", default="c3")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -197,6 +285,10 @@ def main():
     mesh.close()
     del q, dq, r
     torch.cuda.empty_cache()
+    if not args.no_precision:
+        log("[bench] FP64 vs FP32-mixed ...")
+        out["precision"] = precision_block(esdg, W, torch, workload=args.precision_workload)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         log("[bench] timing the CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

@@ -16,6 +16,7 @@
 
 #include "esdg.h"
 #include "esdg_device.hpp"
+#include "esdg_mixed.hpp"
 
 using namespace esdg;
 
@@ -136,6 +137,10 @@ OrderTables make_order_tables(int N)
     for (int a = 0; a < Nq; ++a)
         for (int b = 0; b < Nq; ++b)
             t.T[a][b] = (a == b) ? 0.0 : D[a * Nq + b] - (t.w[b] / t.w[a]) * D[b * Nq + a];
+    for (int a = 0; a < Nq; ++a) {
+        t.winvf[a] = (float)t.winv[a];
+        for (int b = 0; b < Nq; ++b) t.Tf[a][b] = (float)t.T[a][b];
+    }
     return t;
 }
 
@@ -185,6 +190,9 @@ struct esdg_mesh {
     int *d_flag;
     double *h_out;       // pinned, 4 doubles
     int *h_flag;         // pinned
+    float *d_ref_r;      // FP32_MIXED: reference density (FP32 values)
+    float *d_ref_p;      // FP32_MIXED: reference pressure
+    float *d_rr_mom;     // FP32_MIXED: momentum components of R(q_r)
     int64_t red_blocks;
     int64_t footprint;
     // captured two-step graph for esdg_lsrk_run
@@ -221,11 +229,40 @@ const Variant kVariants[] = {
 };
 #undef V
 
+typedef void (*mixed_kernel_t)(MixedParams);
+
+struct MixedVariant {
+    int N, epw, threads;
+    mixed_kernel_t rhs, stage;
+};
+
+#define VM(NN, E)                                                                            \
+    {NN, E, block_threads<NN + 1, E>(), stage_mixed<NN + 1, E, MODE_RHS>,                   \
+     stage_mixed<NN + 1, E, MODE_STAGE>}
+const MixedVariant kMixedVariants[] = {
+    VM(1, 16), VM(2, 7), VM(3, 4), VM(3, 8), VM(4, 2), VM(4, 5),
+    VM(5, 3), VM(6, 2), VM(7, 1), VM(7, 2), VM(8, 1),
+};
+#undef VM
+
 const Variant *find_variant(int N, int epw)
 {
     for (const Variant &v : kVariants)
         if (v.N == N && v.epw == epw) return &v;
     return nullptr;
+}
+
+const MixedVariant *find_mixed_variant(int N, int epw)
+{
+    for (const MixedVariant &v : kMixedVariants)
+        if (v.N == N && v.epw == epw) return &v;
+    return nullptr;
+}
+
+bool has_variant(int precision, int N, int epw)
+{
+    return precision == ESDG_FP32_MIXED ? find_mixed_variant(N, epw) != nullptr
+                                        : find_variant(N, epw) != nullptr;
 }
 
 int default_epw(int N)
@@ -281,15 +318,34 @@ StageParams base_params(const esdg_mesh *m)
     return P;
 }
 
-int launch_stage(esdg_mesh *m, StageParams P)
+int launch_stage_fp64(esdg_mesh *m, StageParams P, int epw)
 {
-    const Variant *v = find_variant(m->N, m->epw);
-    if (!v) return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", m->N, m->epw);
-    const int64_t nb = (m->ne + m->epw - 1) / m->epw;
+    const Variant *v = find_variant(m->N, epw);
+    if (!v) return fail(ESDG_EINVAL, "no FP64 kernel variant for N=%d epw=%d", m->N, epw);
+    const int64_t nb = (m->ne + epw - 1) / epw;
     if (nb > 0x7fffffff) return fail(ESDG_EINVAL, "mesh too large");
     P.nblocks = (int)nb;
     hipLaunchKernelGGL(P.mode == MODE_RHS ? v->rhs : v->stage, dim3((unsigned)nb),
                        dim3(v->threads), 0, m->stream, P);
+    HIP_TRY(hipGetLastError());
+    return ESDG_OK;
+}
+
+int launch_stage(esdg_mesh *m, StageParams P)
+{
+    if (m->desc.precision != ESDG_FP32_MIXED) return launch_stage_fp64(m, P, m->epw);
+    const MixedVariant *v = find_mixed_variant(m->N, m->epw);
+    if (!v) return fail(ESDG_EINVAL, "no mixed kernel variant for N=%d epw=%d", m->N, m->epw);
+    const int64_t nb = (m->ne + m->epw - 1) / m->epw;
+    if (nb > 0x7fffffff) return fail(ESDG_EINVAL, "mesh too large");
+    P.nblocks = (int)nb;
+    MixedParams M;
+    M.s = P;
+    M.ref_r = m->d_ref_r;
+    M.ref_p = m->d_ref_p;
+    M.rr_mom = m->d_rr_mom;
+    hipLaunchKernelGGL(P.mode == MODE_RHS ? v->rhs : v->stage, dim3((unsigned)nb),
+                       dim3(v->threads), 0, m->stream, M);
     HIP_TRY(hipGetLastError());
     return ESDG_OK;
 }
@@ -351,6 +407,37 @@ void drop_graph(esdg_mesh *m)
     m->g_q = m->g_dq = nullptr;
 }
 
+// FP32_MIXED set-up: round the caller's reference to FP32, build the FP64
+// reference state q_r (rho_r, 0, 0, 0, p_r/(gamma-1) + rho_r phi) and keep
+// the momentum components of R(q_r), evaluated once by the FP64 kernel.
+int setup_reference(esdg_mesh *m)
+{
+    const size_t nn = (size_t)m->nn;
+    if (hipMalloc(&m->d_ref_r, sizeof(float) * nn) != hipSuccess ||
+        hipMalloc(&m->d_ref_p, sizeof(float) * nn) != hipSuccess ||
+        hipMalloc(&m->d_rr_mom, sizeof(float) * 3 * nn) != hipSuccess)
+        return fail(ESDG_ENOMEM, "reference buffers (%.1f MB)", 20.0 * nn / 1e6);
+    m->footprint += (int64_t)(20 * nn);
+    GeomParams G = geom(m);
+    const unsigned blocks = (unsigned)((nn + 255) / 256);
+    hipLaunchKernelGGL(reference_state_kernel, dim3(blocks), dim3(256), 0, m->stream, G,
+                       m->desc.ref_rho, m->desc.ref_p, m->d_ref_r, m->d_ref_p, m->d_q2);
+    HIP_TRY(hipGetLastError());
+    StageParams P = base_params(m);
+    P.mode = MODE_RHS;
+    P.q_in = m->d_q2;
+    P.r_out = m->d_r;
+    P.flag = nullptr;
+    const int epw = find_variant(m->N, m->epw) ? m->epw : default_epw(m->N);
+    int rc = launch_stage_fp64(m, P, epw);
+    if (rc) return rc;
+    hipLaunchKernelGGL(reference_rhs_kernel, dim3(blocks), dim3(256), 0, m->stream, m->ne,
+                       m->Np, (const double *)m->d_r, m->d_rr_mom);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    return ESDG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -410,10 +497,15 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         return fail(ESDG_EINVAL, "gamma must be > 1 and gas_R > 0");
     if (d->surface_flux != ESDG_SURF_RUSANOV && d->surface_flux != ESDG_SURF_EC)
         return fail(ESDG_EINVAL, "unknown surface flux %d", d->surface_flux);
-    if (d->precision != ESDG_FP64)
-        return fail(ESDG_ENOTIMPL, "precision %d not available", d->precision);
+    if (d->precision != ESDG_FP64 && d->precision != ESDG_FP32_MIXED)
+        return fail(ESDG_EINVAL, "unknown precision %d", d->precision);
+    if (d->precision == ESDG_FP32_MIXED) {
+        int rc0;
+        if ((rc0 = check_ptr(d->ref_rho, "ref_rho")) || (rc0 = check_ptr(d->ref_p, "ref_p")))
+            return rc0;
+    }
     const int epw = d->epw ? d->epw : default_epw(d->N);
-    if (!find_variant(d->N, epw))
+    if (!has_variant(d->precision, d->N, epw))
         return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", d->N, epw);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -453,6 +545,14 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         esdg_mesh_destroy(m);
         return fail(ESDG_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e8));
     }
+    if (d->precision == ESDG_FP32_MIXED) {
+        rc = setup_reference(m);
+        if (rc) {
+            const std::string msg = g_err;
+            esdg_mesh_destroy(m);
+            return fail(rc, "%s", msg.c_str());
+        }
+    }
     *out = m;
     return ESDG_OK;
 }
@@ -471,6 +571,9 @@ int esdg_mesh_destroy(esdg_mesh_t m)
     if (m->d_partials) (void)hipFree(m->d_partials);
     if (m->d_red_out) (void)hipFree(m->d_red_out);
     if (m->d_flag) (void)hipFree(m->d_flag);
+    if (m->d_ref_r) (void)hipFree(m->d_ref_r);
+    if (m->d_ref_p) (void)hipFree(m->d_ref_p);
+    if (m->d_rr_mom) (void)hipFree(m->d_rr_mom);
     if (m->h_out) (void)hipHostFree(m->h_out);
     if (m->h_flag) (void)hipHostFree(m->h_flag);
     delete m;
@@ -502,7 +605,8 @@ int esdg_set_epw(esdg_mesh_t m, int32_t epw)
     int rc = check_mesh(m);
     if (rc) return rc;
     const int e = epw ? epw : default_epw(m->N);
-    if (!find_variant(m->N, e)) return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", m->N, e);
+    if (!has_variant(m->desc.precision, m->N, e))
+        return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", m->N, e);
     m->epw = e;
     drop_graph(m);
     return ESDG_OK;

@@ -40,6 +40,8 @@ struct OrderTables {
     double w[NQ_MAX];
     double winv[NQ_MAX];
     double T[NQ_MAX][NQ_MAX];  // S_ab / w_a
+    float winvf[NQ_MAX];       // FP32 copies for the mixed-precision kernel
+    float Tf[NQ_MAX][NQ_MAX];
 };
 
 __constant__ OrderTables c_tab[NQ_MAX];  // index N-1
@@ -260,6 +262,30 @@ __device__ __forceinline__ int line_node(int m, int t)
     if (R == 0) return t + NQ * m;                              // m = j + NQ k
     if (R == 1) return (m % NQ) + NQ * t + NQ2 * (m / NQ);      // m = i + NQ k
     return m + NQ2 * t;                                         // m = i + NQ j
+}
+
+// Conservative state on the plus side of the face of element ec in direction
+// R (side 0: minus face, 1: plus face) at the end of the lane's line: the
+// neighbour's coincident node, or the mirror state (rho, m - 2 (m.n) n, E)
+// at a reflecting wall.
+template <int NQ, int R>
+__device__ __forceinline__ void plus_state(const StageParams &P, int m, const int ec[3], int side,
+                                           const Cons &qm, Cons &qp)
+{
+    constexpr int NQ3 = NQ * NQ * NQ;
+    int nb = ec[R] + (side ? 1 : -1);
+    const bool wall = (nb < 0 || nb >= P.K[R]) && !P.periodic[R];
+    if (!wall) {
+        if (nb < 0) nb += P.K[R];
+        if (nb >= P.K[R]) nb -= P.K[R];
+        int cc[3] = {ec[0], ec[1], ec[2]};
+        cc[R] = nb;
+        const int64_t en = cc[0] + (int64_t)P.K[0] * (cc[1] + (int64_t)P.K[1] * cc[2]);
+        load_cons(P.q_in, en, NQ3, line_node<NQ, R>(m, side ? 0 : NQ - 1), qp);
+    } else {
+        qp = qm;
+        qp.v[1 + R] = -qp.v[1 + R];
+    }
 }
 
 // Per-node logarithms of one line, computed only when some pair of the line
