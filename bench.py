@@ -153,6 +153,38 @@ def precision_block(esdg, W, torch, steps=100, workload="c3"):
     return out
 
 
+def serving_block(torch, throughput, n=96, steps=50, budget_gb=24.0, load=1.2, seed=0):
+    """Ensemble serving: a seeded stream of n requests (bubble/channel, K per
+    dimension ~ U{8..40}, N in {3,4,5,7}, FP64 or FP32-mixed, `steps` LSRK
+    steps each) with Poisson arrivals whose offered load is `load` times the
+    measured single-mesh throughput, under an HBM budget below the total
+    footprint."""
+    import tempfile
+    from paper_2605_16684_amd import serving as S
+    probe = S.request_stream(n=n, seed=seed, mean_interarrival=1.0, steps=steps)
+    mean_work = sum(r.nodes * 5 * r.steps for r in probe) / n
+    mean_gap = mean_work / (load * throughput)
+    reqs = S.request_stream(n=n, seed=seed, mean_interarrival=mean_gap, steps=steps)
+    budget = int(budget_gb * 2 ** 30)
+    total = sum(S.footprint_bytes(r) for r in reqs)
+    with tempfile.TemporaryDirectory() as td:
+        tuner = S.Autotuner(os.path.join(td, "epw.json"), target_nodes=1.0e6)
+        t0 = time.perf_counter()
+        for N in (3, 4, 5, 7):
+            for prec in (S.FP64, S.FP32_MIXED):
+                tuner.epw(N, prec)
+        t_tune = time.perf_counter() - t0
+        srv = S.Server(budget, executor=S.GpuExecutor(tuner))
+        st = srv.run(reqs)
+        table = {k: v["epw"] for k, v in tuner.table.items()}
+    out = st.as_dict()
+    out.update({"requests": n, "steps_per_request": steps, "mean_interarrival_s": mean_gap,
+                "offered_load_vs_capacity": load, "total_footprint_bytes": total,
+                "autotune_s": t_tune, "epw_by_bucket": table,
+                "nodes_range": [min(r.nodes for r in reqs), max(r.nodes for r in reqs)]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +197,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP64 vs FP32-mixed comparison")
     ap.add_argument("--precision-workload", default="c3")
+    ap.add_argument("--no-serving", action="store_true", help="skip the ensemble serving run")
+    ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -288,6 +322,10 @@ def main():
     if not args.no_precision:
         log("[bench] FP64 vs FP32-mixed ...")
         out["precision"] = precision_block(esdg, W, torch, workload=args.precision_workload)
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        log("[bench] ensemble serving ...")
+        out["serving"] = serving_block(torch, value, n=args.serving_requests)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("[bench] timing the CPU oracle baseline ...")

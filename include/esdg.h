@@ -174,6 +174,44 @@ const char *esdg_version(void);
  * tensor-product derivatives).  No device work; usable without a GPU. */
 int esdg_lgl_tables(int32_t N, double *xi, double *w, double *D);
 
+/* Elements-per-workgroup values compiled for order N and a precision
+ * (ESDG_FP64 or ESDG_FP32_MIXED): writes up to cap of them to out (may be
+ * NULL) and returns their count, or a negative error.  Host-only. */
+int esdg_epw_options(int32_t N, int32_t precision, int32_t *out, int32_t cap);
+
+/* ---- Packed multi-member stepping (ensemble serving) --------------------
+ * A pack advances several independent meshes ("members") of the same order
+ * N, precision and elements-per-workgroup with one fused stage launch per
+ * LSRK stage: every member's elements are dealt to the workgroups of a
+ * single grid through a device descriptor table, so small members share the
+ * device with large ones.  One step = 5 packed stage launches + a parity
+ * flip, captured once in a HIP graph and replayed (paper Sec. 3: LSRK(5,4);
+ * each member evolves exactly as esdg_lsrk_step would evolve it alone).
+ * Each member owns two caller-allocated state buffers q0/q1 and dq; its
+ * state lives in q0 (parity 0) or q1 (parity 1) and moves to the other
+ * buffer after every step, so after k steps it is in q[parity ^ (k & 1)].
+ * Members and buffers must stay valid until the pack's stream has passed
+ * the last step; calls on one pack must not overlap. */
+typedef struct esdg_pack *esdg_pack_t;
+
+/* Create an empty pack bound to hip_stream (NULL = default stream). */
+int esdg_pack_create(void *hip_stream, esdg_pack_t *out);
+
+/* Synchronise the pack's stream and free it (members are not touched). */
+int esdg_pack_destroy(esdg_pack_t pack);
+
+/* Replace the member set: n meshes (same N, precision, epw, device), each
+ * with q0[i], q1[i], dq[i] (device arrays of its state_len doubles, not
+ * overlapping), time step dt[i], and parity[i] in {0, 1} naming the buffer
+ * that holds its current state.  Synchronises the pack's stream; drops the
+ * captured graph. */
+int esdg_pack_set_members(esdg_pack_t pack, int32_t n, const esdg_mesh_t *meshes,
+                          double *const *q0, double *const *q1, double *const *dq,
+                          const double *dt, const int32_t *parity);
+
+/* nsteps LSRK(5,4) steps of every member (graph replay, asynchronous). */
+int esdg_pack_step(esdg_pack_t pack, int32_t nsteps);
+
 #ifdef __cplusplus
 }
 #endif

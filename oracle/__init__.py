@@ -173,7 +173,7 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.oracle_mesh_destroy(h)
             self._h = None
 

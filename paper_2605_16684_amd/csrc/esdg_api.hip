@@ -209,14 +209,17 @@ namespace {
 // Compiled (N, EPW) variants of the fused stage kernel.
 typedef void (*stage_kernel_t)(StageParams);
 
+typedef void (*packed_kernel_t)(PackLaunch);
+
 struct Variant {
     int N, epw, threads;
     stage_kernel_t rhs, stage;
+    packed_kernel_t packed;
 };
 
 #define V(NN, E)                                                                             \
     {NN, E, block_threads<NN + 1, E>(), stage_fp64<NN + 1, E, MODE_RHS>,                    \
-     stage_fp64<NN + 1, E, MODE_STAGE>}
+     stage_fp64<NN + 1, E, MODE_STAGE>, stage_fp64_packed<NN + 1, E, MODE_STAGE>}
 const Variant kVariants[] = {
     V(1, 8), V(1, 16), V(1, 32),
     V(2, 4), V(2, 7), V(2, 14),
@@ -230,15 +233,17 @@ const Variant kVariants[] = {
 #undef V
 
 typedef void (*mixed_kernel_t)(MixedParams);
+typedef void (*mixed_packed_kernel_t)(PackLaunchMixed);
 
 struct MixedVariant {
     int N, epw, threads;
     mixed_kernel_t rhs, stage;
+    mixed_packed_kernel_t packed;
 };
 
 #define VM(NN, E)                                                                            \
     {NN, E, block_threads<NN + 1, E>(), stage_mixed<NN + 1, E, MODE_RHS>,                   \
-     stage_mixed<NN + 1, E, MODE_STAGE>}
+     stage_mixed<NN + 1, E, MODE_STAGE>, stage_mixed_packed<NN + 1, E, MODE_STAGE>}
 const MixedVariant kMixedVariants[] = {
     VM(1, 16), VM(2, 7), VM(3, 4), VM(3, 8), VM(4, 2), VM(4, 5),
     VM(5, 3), VM(6, 2), VM(7, 1), VM(7, 2), VM(8, 1),
@@ -407,6 +412,28 @@ void drop_graph(esdg_mesh *m)
     m->g_q = m->g_dq = nullptr;
 }
 
+// State-sized scratch of the mesh, allocated on first use: the ping-pong
+// buffer of esdg_lsrk_step/run and the RHS buffer of esdg_entropy.
+int ensure_scratch(esdg_mesh *m, double **buf)
+{
+    if (*buf) return ESDG_OK;
+    const size_t sb = sizeof(double) * (size_t)m->state_len;
+    if (hipMalloc(buf, sb) != hipSuccess) {
+        *buf = nullptr;
+        return fail(ESDG_ENOMEM, "device allocation of %.1f MB failed", sb / 1e6);
+    }
+    m->footprint += (int64_t)sb;
+    return ESDG_OK;
+}
+
+void release_scratch(esdg_mesh *m, double **buf)
+{
+    if (!*buf) return;
+    (void)hipFree(*buf);
+    *buf = nullptr;
+    m->footprint -= (int64_t)(sizeof(double) * (size_t)m->state_len);
+}
+
 // FP32_MIXED set-up: round the caller's reference to FP32, build the FP64
 // reference state q_r (rho_r, 0, 0, 0, p_r/(gamma-1) + rho_r phi) and keep
 // the momentum components of R(q_r), evaluated once by the FP64 kernel.
@@ -418,6 +445,8 @@ int setup_reference(esdg_mesh *m)
         hipMalloc(&m->d_rr_mom, sizeof(float) * 3 * nn) != hipSuccess)
         return fail(ESDG_ENOMEM, "reference buffers (%.1f MB)", 20.0 * nn / 1e6);
     m->footprint += (int64_t)(20 * nn);
+    int rc0;
+    if ((rc0 = ensure_scratch(m, &m->d_q2)) || (rc0 = ensure_scratch(m, &m->d_r))) return rc0;
     GeomParams G = geom(m);
     const unsigned blocks = (unsigned)((nn + 255) / 256);
     hipLaunchKernelGGL(reference_state_kernel, dim3(blocks), dim3(256), 0, m->stream, G,
@@ -435,6 +464,9 @@ int setup_reference(esdg_mesh *m)
                        m->Np, (const double *)m->d_r, m->d_rr_mom);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(m->stream));
+    // the temporaries are re-allocated on demand
+    release_scratch(m, &m->d_q2);
+    release_scratch(m, &m->d_r);
     return ESDG_OK;
 }
 
@@ -527,9 +559,7 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
     m->epw = epw;
     for (int k = 0; k < 3; ++k) m->h[k] = (d->hi[k] - d->lo[k]) / d->K[k];
     m->red_blocks = (m->nn + RED_THREADS - 1) / RED_THREADS;
-    const size_t sb = sizeof(double) * (size_t)m->state_len;
-    hipError_t e1 = hipMalloc(&m->d_q2, sb);
-    hipError_t e2 = hipMalloc(&m->d_r, sb);
+    hipError_t e1 = hipSuccess, e2 = hipSuccess;  // state-sized scratch is allocated on first use
     hipError_t e3 = hipMalloc(&m->d_partials, sizeof(double) * 4 * (size_t)m->red_blocks);
     hipError_t e4 = hipMalloc(&m->d_red_out, sizeof(double) * 4);
     hipError_t e5 = hipMalloc(&m->d_flag, sizeof(int));
@@ -537,9 +567,9 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
     hipError_t e7 = hipHostMalloc(&m->h_flag, sizeof(int), hipHostMallocDefault);
     if (e1 || e2 || e3 || e4 || e5 || e6 || e7) {
         esdg_mesh_destroy(m);
-        return fail(ESDG_ENOMEM, "device allocation of %.1f MB failed", 2.0 * sb / 1e6);
+        return fail(ESDG_ENOMEM, "device allocation of the mesh tables failed");
     }
-    m->footprint = 2 * (int64_t)sb + (int64_t)(sizeof(double) * 4 * m->red_blocks) + 64;
+    m->footprint = (int64_t)(sizeof(double) * 4 * m->red_blocks) + 64;
     hipError_t e8 = hipMemsetAsync(m->d_flag, 0, sizeof(int), m->stream);
     if (e8 != hipSuccess) {
         esdg_mesh_destroy(m);
@@ -661,6 +691,7 @@ int esdg_lsrk_step(esdg_mesh_t m, double *q, double *dq, double t, double dt)
     if (rc || (rc = check_ptr(q, "q")) || (rc = check_ptr(dq, "dq")) || (rc = set_device(m)))
         return rc;
     if (overlaps(q, dq, m->state_len)) return fail(ESDG_EINVAL, "q and dq must not overlap");
+    if ((rc = ensure_scratch(m, &m->d_q2))) return rc;
     rc = enqueue_step(m, q, m->d_q2, dq, dt, true);
     if (rc) return rc;
     // five stages end in the mesh's second buffer
@@ -676,6 +707,7 @@ int esdg_lsrk_run(esdg_mesh_t m, double *q, double *dq, double t0, double dt, in
         return rc;
     if (overlaps(q, dq, m->state_len)) return fail(ESDG_EINVAL, "q and dq must not overlap");
     if (nsteps < 0) return fail(ESDG_EINVAL, "nsteps < 0");
+    if ((rc = ensure_scratch(m, &m->d_q2))) return rc;
     const int pairs = nsteps / 2;
     if (pairs > 0) {
         if (!m->graph_exec || m->g_q != q || m->g_dq != dq || m->g_dt != dt ||
@@ -740,6 +772,7 @@ int esdg_entropy(esdg_mesh_t m, const double *q, double out[4])
     int rc = check_mesh(m);
     if (rc || (rc = check_ptr(q, "q")) || (rc = set_device(m))) return rc;
     if (!out) return fail(ESDG_EINVAL, "out is NULL");
+    if ((rc = ensure_scratch(m, &m->d_r))) return rc;
     rc = esdg_rhs(m, q, m->d_r, 0.0);
     if (rc) return rc;
     GeomParams G = geom(m);
@@ -775,6 +808,248 @@ int esdg_cfl_dt(esdg_mesh_t m, const double *q, double cfl, double *dt_out)
     if (!(smax > 0.0) || !std::isfinite(smax))
         return fail(ESDG_ENONPHYS, "wave speed bound is %g", smax);
     *dt_out = cfl / ((m->N + 1) * smax);
+    return ESDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Packed multi-member stepping (ensemble serving)
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct esdg_pack {
+    int device;
+    hipStream_t stream;
+    int n, N, precision, epw, nblocks, capacity;
+    void *d_members;     // PackMember[] or PackMemberMixed[]
+    int *d_parity;
+    hipGraphExec_t graph;
+};
+
+namespace {
+
+void pack_drop_graph(esdg_pack *p)
+{
+    if (p->graph) {
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+}
+
+int pack_enqueue_step(esdg_pack *p, hipStream_t s)
+{
+    for (int st = 0; st < 5; ++st) {
+        if (p->precision == ESDG_FP32_MIXED) {
+            const MixedVariant *v = find_mixed_variant(p->N, p->epw);
+            if (!v) return fail(ESDG_EINVAL, "no mixed kernel variant for N=%d epw=%d", p->N, p->epw);
+            PackLaunchMixed L;
+            L.members = (const PackMemberMixed *)p->d_members;
+            L.parity = p->d_parity;
+            L.n_members = p->n;
+            L.nblocks = p->nblocks;
+            L.stage = st;
+            L.mode = MODE_STAGE;
+            L.A = kA[st];
+            L.B = kB[st];
+            hipLaunchKernelGGL(v->packed, dim3((unsigned)p->nblocks), dim3(v->threads), 0, s, L);
+        } else {
+            const Variant *v = find_variant(p->N, p->epw);
+            if (!v) return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", p->N, p->epw);
+            PackLaunch L;
+            L.members = (const PackMember *)p->d_members;
+            L.parity = p->d_parity;
+            L.n_members = p->n;
+            L.nblocks = p->nblocks;
+            L.stage = st;
+            L.mode = MODE_STAGE;
+            L.A = kA[st];
+            L.B = kB[st];
+            hipLaunchKernelGGL(v->packed, dim3((unsigned)p->nblocks), dim3(v->threads), 0, s, L);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(pack_flip_kernel, dim3((unsigned)((p->n + 255) / 256)), dim3(256), 0, s,
+                       p->d_parity, p->n);
+    HIP_TRY(hipGetLastError());
+    return ESDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int esdg_epw_options(int32_t N, int32_t precision, int32_t *out, int32_t cap)
+{
+    if (N < 1 || N > NQ_MAX - 1) return fail(ESDG_EINVAL, "N=%d outside 1..8", N);
+    int cnt = 0;
+    if (precision == ESDG_FP32_MIXED) {
+        for (const MixedVariant &v : kMixedVariants)
+            if (v.N == N) {
+                if (out && cnt < cap) out[cnt] = v.epw;
+                ++cnt;
+            }
+    } else if (precision == ESDG_FP64) {
+        for (const Variant &v : kVariants)
+            if (v.N == N) {
+                if (out && cnt < cap) out[cnt] = v.epw;
+                ++cnt;
+            }
+    } else {
+        return fail(ESDG_EINVAL, "unknown precision %d", precision);
+    }
+    return cnt;
+}
+
+int esdg_pack_create(void *hip_stream, esdg_pack_t *out)
+{
+    if (!out) return fail(ESDG_EINVAL, "NULL argument");
+    esdg_pack *p = new (std::nothrow) esdg_pack();
+    if (!p) return fail(ESDG_ENOMEM, "host allocation failed");
+    std::memset(p, 0, sizeof *p);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(ESDG_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    p->device = dev;
+    p->stream = (hipStream_t)hip_stream;
+    *out = p;
+    return ESDG_OK;
+}
+
+int esdg_pack_destroy(esdg_pack_t p)
+{
+    if (!p) return ESDG_OK;
+    int rc = ESDG_OK;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) rc = fail(ESDG_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    pack_drop_graph(p);
+    if (p->d_members) (void)hipFree(p->d_members);
+    if (p->d_parity) (void)hipFree(p->d_parity);
+    delete p;
+    return rc;
+}
+
+int esdg_pack_set_members(esdg_pack_t p, int32_t n, const esdg_mesh_t *meshes, double *const *q0,
+                          double *const *q1, double *const *dq, const double *dt,
+                          const int32_t *parity)
+{
+    if (!p) return fail(ESDG_EINVAL, "NULL pack");
+    if (n < 1) return fail(ESDG_EINVAL, "a pack needs at least one member");
+    if (!meshes || !q0 || !q1 || !dq || !dt || !parity) return fail(ESDG_EINVAL, "NULL array");
+    const esdg_mesh *m0 = meshes[0];
+    if (!m0) return fail(ESDG_EINVAL, "NULL mesh");
+    const int N = m0->N, prec = m0->desc.precision, epw = m0->epw;
+    int64_t blocks = 0;
+    const bool mixed = prec == ESDG_FP32_MIXED;
+    std::string tab(mixed ? sizeof(PackMemberMixed) * n : sizeof(PackMember) * n, '\0');
+    for (int i = 0; i < n; ++i) {
+        esdg_mesh *m = meshes[i];
+        if (!m) return fail(ESDG_EINVAL, "member %d: NULL mesh", i);
+        if (m->N != N || m->desc.precision != prec || m->epw != epw || m->device != p->device)
+            return fail(ESDG_EINVAL, "member %d: N, precision, epw and device must match", i);
+        int rc;
+        if ((rc = check_ptr(q0[i], "q0")) || (rc = check_ptr(q1[i], "q1")) ||
+            (rc = check_ptr(dq[i], "dq")))
+            return rc;
+        if (overlaps(q0[i], q1[i], m->state_len) || overlaps(q0[i], dq[i], m->state_len) ||
+            overlaps(q1[i], dq[i], m->state_len))
+            return fail(ESDG_EINVAL, "member %d: q0, q1 and dq must not overlap", i);
+        if (parity[i] != 0 && parity[i] != 1)
+            return fail(ESDG_EINVAL, "member %d: parity must be 0 or 1", i);
+        StageParams P = base_params(m);
+        P.mode = MODE_STAGE;
+        P.dq = dq[i];
+        P.dt = dt[i];
+        P.nblocks = (int)((m->ne + epw - 1) / epw);
+        if (mixed) {
+            PackMemberMixed pm;
+            std::memset(&pm, 0, sizeof pm);
+            pm.M.s = P;
+            pm.M.ref_r = m->d_ref_r;
+            pm.M.ref_p = m->d_ref_p;
+            pm.M.rr_mom = m->d_rr_mom;
+            pm.bufs[0] = q0[i];
+            pm.bufs[1] = q1[i];
+            pm.block_begin = (int)blocks;
+            std::memcpy(&tab[sizeof(pm) * i], &pm, sizeof pm);
+        } else {
+            PackMember pm;
+            std::memset(&pm, 0, sizeof pm);
+            pm.P = P;
+            pm.bufs[0] = q0[i];
+            pm.bufs[1] = q1[i];
+            pm.block_begin = (int)blocks;
+            std::memcpy(&tab[sizeof(pm) * i], &pm, sizeof pm);
+        }
+        blocks += P.nblocks;
+        if (blocks > 0x7fffffff) return fail(ESDG_EINVAL, "pack too large");
+    }
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) HIP_TRY(hipSetDevice(p->device));
+    // the previous step may still read the old table
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    pack_drop_graph(p);
+    if (n > p->capacity) {
+        if (p->d_members) (void)hipFree(p->d_members);
+        if (p->d_parity) (void)hipFree(p->d_parity);
+        p->d_members = nullptr;
+        p->d_parity = nullptr;
+        p->capacity = 0;
+        const int cap = std::max(n, 2 * p->capacity);
+        if (hipMalloc(&p->d_members, std::max(sizeof(PackMember), sizeof(PackMemberMixed)) * cap) !=
+                hipSuccess ||
+            hipMalloc(&p->d_parity, sizeof(int) * cap) != hipSuccess)
+            return fail(ESDG_ENOMEM, "pack table allocation failed");
+        p->capacity = cap;
+    }
+    HIP_TRY(hipMemcpyAsync(p->d_members, tab.data(), tab.size(), hipMemcpyHostToDevice,
+                           p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_parity, parity, sizeof(int32_t) * n, hipMemcpyHostToDevice,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->n = n;
+    p->N = N;
+    p->precision = prec;
+    p->epw = epw;
+    p->nblocks = (int)blocks;
+    return ESDG_OK;
+}
+
+int esdg_pack_step(esdg_pack_t p, int32_t nsteps)
+{
+    if (!p) return fail(ESDG_EINVAL, "NULL pack");
+    if (nsteps < 0) return fail(ESDG_EINVAL, "nsteps < 0");
+    if (p->n < 1) return fail(ESDG_EINVAL, "pack has no members");
+    if (nsteps == 0) return ESDG_OK;
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) HIP_TRY(hipSetDevice(p->device));
+    if (!p->graph) {
+        hipStream_t cs;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t eb = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc = ESDG_OK;
+        hipGraph_t graph = nullptr;
+        if (eb == hipSuccess) rc = pack_enqueue_step(p, cs);
+        hipError_t ee = (eb == hipSuccess) ? hipStreamEndCapture(cs, &graph) : eb;
+        (void)hipStreamDestroy(cs);
+        if (eb != hipSuccess) return fail(ESDG_EHIP, "capture: %s", hipGetErrorString(eb));
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ee != hipSuccess) return fail(ESDG_EHIP, "end capture: %s", hipGetErrorString(ee));
+        hipError_t ei = hipGraphInstantiate(&p->graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            p->graph = nullptr;
+            return fail(ESDG_EHIP, "graph instantiate: %s", hipGetErrorString(ei));
+        }
+    }
+    for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(p->graph, p->stream));
     return ESDG_OK;
 }
 

@@ -415,10 +415,11 @@ constexpr int block_threads()
     return ((EPW * NQ * NQ + 63) / 64) * 64;
 }
 
-// One workgroup handles EPW elements; lane (el, m) owns line m of element el
-// in each of the three phases.  LDS holds only the cross-phase accumulator.
+// One workgroup handles EPW elements (logical block lb of the mesh); lane
+// (el, m) owns line m of element el in each of the three phases.  LDS holds
+// only the cross-phase accumulator.
 template <int NQ, int EPW, int MODE>
-__global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const StageParams P)
+__device__ __forceinline__ void stage_body(const StageParams &P, int lb)
 {
     constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
     __shared__ double sacc[5][EPW][NQ3];
@@ -427,7 +428,6 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
     const int tid = threadIdx.x;
     const int el = tid / NQ2;
     const int m = tid - el * NQ2;
-    const int lb = xcd_remap(blockIdx.x, P.nblocks);
     const int64_t e = (int64_t)lb * EPW + el;
     const bool act = (el < EPW) && (e < P.ne);
 
@@ -564,6 +564,67 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const S
         }
         if (bad) atomicOr(P.flag, 1);
     }
+}
+
+template <int NQ, int EPW, int MODE>
+__global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const StageParams P)
+{
+    stage_body<NQ, EPW, MODE>(P, xcd_remap(blockIdx.x, P.nblocks));
+}
+
+// Packed launches over several meshes of the same order (ensemble serving).
+// Member i owns logical blocks [begin_i, begin_{i+1}) of the launch and keeps
+// its state in bufs[parity_i] (the other buffer is the ping-pong target).
+struct PackMember {
+    StageParams P;       // geometry, flags, dq, dt of the member
+    double *bufs[2];     // the member's two state buffers
+    int block_begin;     // first logical block of the member in the launch
+    int pad;
+};
+
+struct PackLaunch {
+    const PackMember *members;
+    const int *parity;   // per member: which buffer holds the current state
+    int n_members;
+    int nblocks;         // total blocks of the launch
+    int stage;           // 0..4 within the step
+    int mode;
+    double A, B;
+};
+
+// Member owning logical block gb: last i with begin_i <= gb.
+__device__ __forceinline__ int pack_member(const PackLaunch &L, int gb)
+{
+    int lo = 0, hi = L.n_members - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.members[mid].block_begin <= gb) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NQ, int EPW, int MODE>
+__global__ void __launch_bounds__((block_threads<NQ, EPW>()))
+    stage_fp64_packed(const PackLaunch L)
+{
+    const int gb = xcd_remap(blockIdx.x, L.nblocks);
+    const int i = pack_member(L, gb);
+    const PackMember &pm = L.members[i];
+    StageParams P = pm.P;
+    const int par = L.parity[i];
+    P.q_in = pm.bufs[par ^ (L.stage & 1)];
+    P.q_out = pm.bufs[par ^ ((L.stage + 1) & 1)];
+    P.A = L.A;
+    P.B = L.B;
+    stage_body<NQ, EPW, MODE>(P, gb - pm.block_begin);
+}
+
+// After the fifth stage each member's state sits in its other buffer.
+__global__ void pack_flip_kernel(int *parity, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) parity[i] ^= 1;
 }
 
 // ---------------------------------------------------------------------------

@@ -297,7 +297,7 @@ __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const Ord
 }
 
 template <int NQ, int EPW, int MODE>
-__global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_mixed(const MixedParams M)
+__device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
 {
     constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
     __shared__ float sacc[5][EPW][NQ3];
@@ -307,7 +307,6 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_mixed(const 
     const int tid = threadIdx.x;
     const int el = tid / NQ2;
     const int m = tid - el * NQ2;
-    const int lb = xcd_remap(blockIdx.x, P.nblocks);
     const int64_t e = (int64_t)lb * EPW + el;
     const bool act = (el < EPW) && (e < P.ne);
 
@@ -451,6 +450,50 @@ __global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_mixed(const 
         }
         if (bad) atomicOr(P.flag, 1);
     }
+}
+
+template <int NQ, int EPW, int MODE>
+__global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_mixed(const MixedParams M)
+{
+    stage_mixed_body<NQ, EPW, MODE>(M, xcd_remap(blockIdx.x, M.s.nblocks));
+}
+
+struct PackMemberMixed {
+    MixedParams M;
+    double *bufs[2];
+    int block_begin;
+    int pad;
+};
+
+struct PackLaunchMixed {
+    const PackMemberMixed *members;
+    const int *parity;
+    int n_members;
+    int nblocks;
+    int stage;
+    int mode;
+    double A, B;
+};
+
+template <int NQ, int EPW, int MODE>
+__global__ void __launch_bounds__((block_threads<NQ, EPW>()))
+    stage_mixed_packed(const PackLaunchMixed L)
+{
+    const int gb = xcd_remap(blockIdx.x, L.nblocks);
+    int lo = 0, hi = L.n_members - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.members[mid].block_begin <= gb) lo = mid;
+        else hi = mid - 1;
+    }
+    const PackMemberMixed &pm = L.members[lo];
+    MixedParams M = pm.M;
+    const int par = L.parity[lo];
+    M.s.q_in = pm.bufs[par ^ (L.stage & 1)];
+    M.s.q_out = pm.bufs[par ^ ((L.stage + 1) & 1)];
+    M.s.A = L.A;
+    M.s.B = L.B;
+    stage_mixed_body<NQ, EPW, MODE>(M, gb - pm.block_begin);
 }
 
 // Reference state as a conservative FP64 state (rho_r, 0, 0, 0, p_r/(gamma-1)

@@ -75,6 +75,13 @@ SIGNATURES = {
     "esdg_version": (C.c_char_p, []),
     "esdg_lgl_tables": (C.c_int, [C.c_int32, _dp, _dp, _dp]),
     "esdg_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "esdg_epw_options": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
+    "esdg_pack_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "esdg_pack_destroy": (C.c_int, [C.c_void_p]),
+    "esdg_pack_set_members": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
+                                        C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                        C.POINTER(C.c_void_p), _dp, C.POINTER(C.c_int32)]),
+    "esdg_pack_step": (C.c_int, [C.c_void_p, C.c_int32]),
 }
 
 
@@ -111,6 +118,16 @@ def lgl_tables(N: int):
     _check(lib.esdg_lgl_tables(N, x.ctypes.data_as(_dp), w.ctypes.data_as(_dp),
                                D.ctypes.data_as(_dp)))
     return x, w, D.reshape(N + 1, N + 1)
+
+
+def epw_options(N: int, precision: int = FP64):
+    """Elements-per-workgroup values compiled for order N and a precision."""
+    n = lib.esdg_epw_options(N, precision, None, 0)
+    if n < 0:
+        _check(n)
+    buf = (C.c_int32 * max(n, 1))()
+    lib.esdg_epw_options(N, precision, buf, n)
+    return [buf[i] for i in range(n)]
 
 
 def copy(src, dst):
@@ -242,3 +259,52 @@ class Mesh:
     def check(self):
         self._bind()
         _check(lib.esdg_check(self._h))
+
+
+class Pack:
+    """Packed multi-member LSRK stepping on one stream (ensemble serving).
+
+    Members share N, precision and elements per workgroup.  Each member i
+    has two state buffers (q0[i], q1[i]); after k steps its state is in
+    buffer parity[i] ^ (k & 1)."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib.esdg_pack_create(C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self._keep = None
+        self.n = 0
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib.esdg_pack_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_members(self, meshes, q0, q1, dq, dts, parity):
+        n = len(meshes)
+        arr = lambda T, vals: (T * n)(*vals)
+        mh = arr(C.c_void_p, [m._h.value for m in meshes])
+        for m, a, b, d in zip(meshes, q0, q1, dq):
+            m._state(a, "q0")
+            m._state(b, "q1")
+            m._state(d, "dq")
+        p0 = arr(C.c_void_p, [t.data_ptr() for t in q0])
+        p1 = arr(C.c_void_p, [t.data_ptr() for t in q1])
+        pd = arr(C.c_void_p, [t.data_ptr() for t in dq])
+        dt = (C.c_double * n)(*[float(x) for x in dts])
+        par = arr(C.c_int32, [int(x) for x in parity])
+        _check(lib.esdg_pack_set_members(self._h, n, mh, p0, p1, pd, dt, par))
+        self._keep = (list(meshes), list(q0), list(q1), list(dq))
+        self.n = n
+
+    def step(self, nsteps: int = 1):
+        _check(lib.esdg_pack_step(self._h, nsteps))

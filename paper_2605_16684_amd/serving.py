@@ -1,0 +1,462 @@
+"""Continuous-batching ensemble server for the ES-DGSEM stepper.
+
+Requests (ensemble members) arrive over time, each a mesh of its own size
+and order with a seeded initial state and a number of LSRK(5,4) steps.  The
+server
+
+* admits arrived requests while their device footprint fits the HBM budget
+  (FIFO with backfill: a request that does not fit does not block smaller
+  ones behind it), keeping every member's state resident on the device;
+* groups members by (N, precision) into buckets; each bucket is one packed
+  launch per stage over all its members (``esdg.Pack``: a device descriptor
+  table, one step = 5 packed stage kernels + a parity flip captured in a
+  HIP graph) on its own stream, so buckets overlap on the device;
+* advances every active member by one step per scheduling round, admits new
+  arrivals between rounds as memory frees, and retires members that reach
+  their step count;
+* picks elements per workgroup per (N, precision) from an autotuner that
+  times the compiled variants and caches the choice in JSON;
+* reports per-member step latency (completion of step s minus completion of
+  step s-1, or of the admission for s = 1) as p50/p99 over all member-steps,
+  aggregate DOF*RHS/s (sum of nodes x 5 x steps / makespan), queue waits and
+  end-to-end latency.
+
+The scheduler is written against a small executor interface: ``GpuExecutor``
+drives the library; ``FakeExecutor`` simulates step durations from a cost
+model so that admission, packing, eviction and the statistics are testable
+on a machine without a GPU.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+import os
+import time
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import workloads as W
+
+FP64, FP32_MIXED = 0, 1
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    kind: str                  # "bubble" | "channel"
+    K: Tuple[int, int, int]
+    N: int
+    precision: int             # FP64 | FP32_MIXED
+    seed: int
+    steps: int
+    arrival: float = 0.0       # seconds after the start of the run
+
+    def spec(self) -> W.MeshSpec:
+        if self.kind == "bubble":
+            return W.rising_bubble(N=self.N, K=self.K).mesh
+        if self.kind == "channel":
+            return W.channel(N=self.N, K=self.K).mesh
+        raise ValueError(self.kind)
+
+    @property
+    def nodes(self) -> int:
+        return self.K[0] * self.K[1] * self.K[2] * (self.N + 1) ** 3
+
+    @property
+    def key(self):
+        return (self.N, self.precision)
+
+
+def footprint_bytes(req: Request) -> int:
+    """Steady device footprint of a member: two state buffers and dq
+    (3 x 40 B per node), the mesh's reduction partials (4 doubles per 256
+    nodes), and for FP32-mixed the FP32 reference and R(q_r) momentum
+    (20 B per node)."""
+    n = req.nodes
+    b = 120 * n + 4 * 8 * (n // 256 + 1) + 4096
+    if req.precision == FP32_MIXED:
+        b += 20 * n
+    return b
+
+
+def request_stream(n=96, seed=0, mean_interarrival=0.05, steps=50, kmin=8, kmax=40,
+                   orders=(3, 4, 5, 7)):
+    """Seeded ensemble request stream: Poisson arrivals, kind bubble/channel
+    with probability 1/2, elements per dimension ~ U{kmin..kmax} independently,
+    N uniform over `orders`, FP64 or FP32-mixed with probability 1/2, seed =
+    request id."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(mean_interarrival))
+        kind = "bubble" if rng.uniform() < 0.5 else "channel"
+        K = tuple(int(k) for k in rng.integers(kmin, kmax + 1, size=3))
+        N = int(rng.choice(orders))
+        prec = FP32_MIXED if rng.uniform() < 0.5 else FP64
+        out.append(Request(i, kind, K, N, prec, i, steps, t))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Autotuner
+# ---------------------------------------------------------------------------
+
+class Autotuner:
+    """Elements per workgroup per (N, precision), chosen by timing the
+    compiled variants on a bubble mesh of about `target_nodes` nodes and
+    cached in a JSON file."""
+
+    def __init__(self, cache_path: Optional[str] = None, target_nodes: float = 2.0e6):
+        self.cache_path = cache_path
+        self.target_nodes = target_nodes
+        self.table: Dict[str, dict] = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.table = json.load(f)
+
+    @staticmethod
+    def _key(N, precision):
+        return f"N{N}_{'mixed' if precision == FP32_MIXED else 'fp64'}"
+
+    def epw(self, N: int, precision: int) -> int:
+        k = self._key(N, precision)
+        if k not in self.table:
+            self.table[k] = self.tune(N, precision)
+            self.save()
+        return int(self.table[k]["epw"])
+
+    def save(self):
+        if self.cache_path:
+            d = os.path.dirname(os.path.abspath(self.cache_path))
+            os.makedirs(d, exist_ok=True)
+            with open(self.cache_path, "w") as f:
+                json.dump(self.table, f, indent=1, sort_keys=True)
+
+    def tune(self, N: int, precision: int, reps: int = 5) -> dict:
+        import torch
+        from . import esdg
+        opts = esdg.epw_options(N, precision)
+        k = max(2, int(round((self.target_nodes / (N + 1) ** 3) ** (1.0 / 3.0))))
+        req = Request(-1, "bubble", (k, k, k), N, precision, 0, 1)
+        timings = {}
+        for e in opts:
+            m, q, _ = _make_member_mesh(req, epw=e)
+            r = torch.empty_like(q)
+            for _ in range(2):
+                m.rhs(q, r)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                m.rhs(q, r)
+            b.record()
+            torch.cuda.synchronize()
+            timings[str(e)] = a.elapsed_time(b) / reps
+            m.close()
+            del q, r
+        best = min(timings, key=timings.get)
+        return {"epw": int(best), "ms": timings, "nodes": req.nodes}
+
+
+def _make_member_mesh(req: Request, epw: int = 0):
+    """Library mesh, initial state (built in device memory) and the FP32-mixed
+    reference arrays of a request."""
+    import torch
+    from . import esdg
+    spec = req.spec()
+    if req.precision == FP32_MIXED:
+        probe = esdg.Mesh(spec, epw=0)
+        xyz = probe.coords()
+        probe.close()
+        rr, pr = W.reference_state(xyz, spec, req.kind)
+        m = esdg.Mesh(spec, precision=esdg.FP32_MIXED, ref_rho=rr.contiguous(),
+                      ref_p=pr.contiguous(), epw=epw)
+        m._refs = None  # the library copied the reference at creation
+    else:
+        m = esdg.Mesh(spec, epw=epw)
+        xyz = m.coords()
+    q = W.make_state(req.kind, xyz, spec, seed=req.seed).contiguous()
+    return m, q, xyz
+
+
+# ---------------------------------------------------------------------------
+# Executors
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Member:
+    req: Request
+    footprint: int
+    handle: object = None          # executor's per-member object
+    admitted: float = 0.0          # host time of admission
+    last_done: float = 0.0         # device time of the last completed step (or admission)
+    steps_done: int = 0
+    latencies: List[float] = dataclasses.field(default_factory=list)
+    finished: float = 0.0
+
+
+class GpuExecutor:
+    """Drives libesdg: one Pack and one stream per (N, precision) bucket."""
+
+    def __init__(self, autotuner: Optional[Autotuner] = None, keep_results: bool = False):
+        import torch
+        self.torch = torch
+        self.autotuner = autotuner or Autotuner()
+        self.keep_results = keep_results
+        self.buckets: Dict[tuple, dict] = {}
+        self.t0_host = time.perf_counter()
+        self.ev0 = torch.cuda.Event(enable_timing=True)
+        self.ev0.record()
+        torch.cuda.synchronize()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0_host
+
+    def _dev_time(self, ev) -> float:
+        return self.ev0.elapsed_time(ev) * 1e-3
+
+    def admit(self, req: Request):
+        torch = self.torch
+        epw = self.autotuner.epw(req.N, req.precision)
+        m, q, xyz = _make_member_mesh(req, epw=epw)
+        del xyz
+        dt = m.cfl_dt(q, 0.5)
+        q1 = torch.empty_like(q)
+        dq = torch.zeros_like(q)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        ev.synchronize()
+        return {"mesh": m, "bufs": [q, q1], "dq": dq, "dt": dt, "parity": 0}, self._dev_time(ev)
+
+    def set_bucket(self, key, members: List[Member]):
+        from . import esdg
+        torch = self.torch
+        b = self.buckets.get(key)
+        if b is None:
+            stream = torch.cuda.Stream()
+            b = {"stream": stream, "pack": None}
+            self.buckets[key] = b
+        with torch.cuda.stream(b["stream"]):
+            if b["pack"] is None:
+                b["pack"] = esdg.Pack(b["stream"])
+            # states written on the default stream (initial states) must be
+            # visible to the bucket stream
+            b["stream"].wait_stream(torch.cuda.default_stream())
+            hs = [mb.handle for mb in members]
+            b["pack"].set_members([h["mesh"] for h in hs], [h["bufs"][0] for h in hs],
+                                  [h["bufs"][1] for h in hs], [h["dq"] for h in hs],
+                                  [h["dt"] for h in hs], [h["parity"] for h in hs])
+        b["members"] = list(members)
+
+    def drop_bucket(self, key):
+        b = self.buckets.pop(key, None)
+        if b and b["pack"] is not None:
+            b["pack"].close()
+
+    def launch_step(self, key):
+        torch = self.torch
+        b = self.buckets[key]
+        with torch.cuda.stream(b["stream"]):
+            b["pack"].step(1)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(b["stream"])
+        for mb in b["members"]:
+            mb.handle["parity"] ^= 1
+        return ev
+
+    def wait(self, tokens: Dict[tuple, object]) -> Dict[tuple, float]:
+        out = {}
+        for key, ev in tokens.items():
+            ev.synchronize()
+            out[key] = self._dev_time(ev)
+        return out
+
+    def release(self, mb: Member):
+        h = mb.handle
+        result = None
+        if self.keep_results:
+            result = h["bufs"][h["parity"]].cpu().numpy()
+        h["mesh"].close()
+        mb.handle = None
+        return result
+
+
+class FakeExecutor:
+    """Simulated device: a step of a bucket takes overhead + sum over its
+    members of nodes x cost(N, precision); buckets launched in one round run
+    back to back.  Time is virtual."""
+
+    def __init__(self, cost_per_node=None, overhead=20e-6, admit_cost=1e-3, fail_on=None):
+        self.cost = cost_per_node or (lambda N, prec: 5 * 1e-10 * (1.0 if prec == FP64 else 0.8))
+        self.overhead = overhead
+        self.admit_cost = admit_cost
+        self.clock = 0.0
+        self.buckets: Dict[tuple, List[Member]] = {}
+        self.fail_on = fail_on or set()
+
+    def now(self) -> float:
+        return self.clock
+
+    def advance_to(self, t):
+        self.clock = max(self.clock, t)
+
+    def admit(self, req: Request):
+        if req.rid in self.fail_on:
+            raise RuntimeError(f"simulated failure admitting request {req.rid}")
+        self.clock += self.admit_cost
+        return {"parity": 0}, self.clock
+
+    def set_bucket(self, key, members):
+        self.buckets[key] = list(members)
+
+    def drop_bucket(self, key):
+        self.buckets.pop(key, None)
+
+    def launch_step(self, key):
+        ms = self.buckets[key]
+        return self.overhead + sum(mb.req.nodes * self.cost(*key) for mb in ms)
+
+    def wait(self, tokens):
+        out = {}
+        for key, dur in tokens.items():
+            self.clock += dur
+            out[key] = self.clock
+        return out
+
+    def release(self, mb):
+        return None
+
+
+# ---------------------------------------------------------------------------
+# Scheduler
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class RunStats:
+    n_requests: int
+    n_completed: int
+    n_rejected: int
+    makespan_s: float
+    aggregate_dof_rhs_per_s: float
+    step_latency_p50_ms: float
+    step_latency_p99_ms: float
+    queue_wait_p50_ms: float
+    queue_wait_p99_ms: float
+    e2e_latency_mean_s: float
+    peak_footprint_bytes: int
+    hbm_budget_bytes: int
+    rounds: int
+    max_concurrent_members: int
+    buckets_seen: int
+
+    def as_dict(self):
+        return dataclasses.asdict(self)
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: int, executor=None, autotuner: Optional[Autotuner] = None):
+        self.budget = int(hbm_budget_bytes)
+        self.ex = executor if executor is not None else GpuExecutor(autotuner)
+        self.results: Dict[int, object] = {}
+        self.members: Dict[int, Member] = {}
+
+    def run(self, requests: List[Request], realtime: bool = True) -> RunStats:
+        """Serve the stream until every request has completed (or was
+        rejected for exceeding the whole budget)."""
+        ex = self.ex
+        pending = sorted(requests, key=lambda r: r.arrival)
+        queue: List[Request] = []
+        active: Dict[tuple, List[Member]] = {}
+        dirty = set()
+        used = peak = 0
+        rejected = 0
+        done: List[Member] = []
+        rounds = max_conc = 0
+        buckets_seen = set()
+        t_start = ex.now()
+        while pending or queue or any(active.values()):
+            now = ex.now() - t_start
+            while pending and pending[0].arrival <= now:
+                r = pending.pop(0)
+                if footprint_bytes(r) > self.budget:
+                    rejected += 1
+                    continue
+                queue.append(r)
+            # admission: FIFO with backfill
+            for r in list(queue):
+                fp = footprint_bytes(r)
+                if used + fp > self.budget:
+                    continue
+                try:
+                    handle, t_adm = ex.admit(r)
+                except Exception:
+                    queue.remove(r)
+                    rejected += 1
+                    continue
+                queue.remove(r)
+                mb = Member(r, fp, handle, admitted=ex.now() - t_start, last_done=t_adm)
+                used += fp
+                peak = max(peak, used)
+                active.setdefault(r.key, []).append(mb)
+                self.members[r.rid] = mb
+                dirty.add(r.key)
+            n_act = sum(len(v) for v in active.values())
+            if n_act == 0:
+                if not pending and not queue:
+                    break
+                if pending:
+                    wait = pending[0].arrival - (ex.now() - t_start)
+                    if wait > 0:
+                        if realtime and hasattr(ex, "torch"):
+                            time.sleep(min(wait, 0.05))
+                        elif hasattr(ex, "advance_to"):
+                            ex.advance_to(t_start + pending[0].arrival)
+                        else:
+                            time.sleep(min(wait, 0.05))
+                continue
+            max_conc = max(max_conc, n_act)
+            for key in list(dirty):
+                if active.get(key):
+                    ex.set_bucket(key, active[key])
+                    buckets_seen.add(key)
+                else:
+                    ex.drop_bucket(key)
+                    active.pop(key, None)
+            dirty.clear()
+            tokens = {key: ex.launch_step(key) for key, ms in active.items() if ms}
+            times = ex.wait(tokens)
+            rounds += 1
+            for key, t_end in times.items():
+                for mb in list(active[key]):
+                    mb.latencies.append(t_end - mb.last_done)
+                    mb.last_done = t_end
+                    mb.steps_done += 1
+                    if mb.steps_done >= mb.req.steps:
+                        mb.finished = ex.now() - t_start
+                        self.results[mb.req.rid] = ex.release(mb)
+                        active[key].remove(mb)
+                        used -= mb.footprint
+                        done.append(mb)
+                        dirty.add(key)
+        for key in list(active):
+            ex.drop_bucket(key)
+        makespan = max((mb.finished for mb in done), default=0.0)
+        first = min((r.arrival for r in requests), default=0.0)
+        span = max(makespan - first, 1e-12)
+        lat = np.array([x for mb in done for x in mb.latencies]) if done else np.zeros(1)
+        waits = np.array([mb.admitted - mb.req.arrival for mb in done]) if done else np.zeros(1)
+        e2e = np.array([mb.finished - mb.req.arrival for mb in done]) if done else np.zeros(1)
+        work = sum(mb.req.nodes * 5 * mb.steps_done for mb in done)
+        return RunStats(
+            n_requests=len(requests), n_completed=len(done), n_rejected=rejected,
+            makespan_s=span, aggregate_dof_rhs_per_s=work / span,
+            step_latency_p50_ms=float(np.percentile(lat, 50) * 1e3),
+            step_latency_p99_ms=float(np.percentile(lat, 99) * 1e3),
+            queue_wait_p50_ms=float(np.percentile(waits, 50) * 1e3),
+            queue_wait_p99_ms=float(np.percentile(waits, 99) * 1e3),
+            e2e_latency_mean_s=float(e2e.mean()), peak_footprint_bytes=int(peak),
+            hbm_budget_bytes=self.budget, rounds=rounds, max_concurrent_members=max_conc,
+            buckets_seen=len(buckets_seen))

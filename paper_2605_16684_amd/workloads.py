@@ -23,6 +23,16 @@ from typing import Optional, Tuple
 
 import numpy as np
 
+
+def _xp(a):
+    """numpy for numpy arrays, torch for torch tensors (states can be built
+    directly in device memory)."""
+    if type(a).__module__.startswith("torch"):
+        import torch
+        return torch
+    return np
+
+
 GAMMA = 1.4
 GAS_R = 287.0
 GRAV = 9.81
@@ -101,18 +111,14 @@ def _energy(rho, u, v, w, p, z, gamma=GAMMA, grav=GRAV):
 
 
 def _pack(rho, u, v, w, p, z, gamma=GAMMA, grav=GRAV):
-    q = np.empty((rho.shape[0], 5, rho.shape[1]))
-    q[:, 0] = rho
-    q[:, 1] = rho * u
-    q[:, 2] = rho * v
-    q[:, 3] = rho * w
-    q[:, 4] = _energy(rho, u, v, w, p, z, gamma, grav)
-    return q
+    xp = _xp(rho)
+    return xp.stack([rho, rho * u, rho * v, rho * w, _energy(rho, u, v, w, p, z, gamma, grav)],
+                    axis=1)
 
 
 def isothermal(z, T=300.0, p0=P0, gas_R=GAS_R, grav=GRAV):
     """Isothermal hydrostatic profile: p = p0 exp(-g z/(R T)), rho = p/(R T)."""
-    p = p0 * np.exp(-grav * z / (gas_R * T))
+    p = p0 * _xp(z).exp(-grav * z / (gas_R * T))
     return p / (gas_R * T), p
 
 
@@ -128,13 +134,16 @@ def _fourier(rng, x, y, z, L, nmodes=4):
     """Smooth seeded field: sum of nmodes plane waves with integer wavenumbers
     1..3 per direction over the box lengths L, random phases, amplitudes in
     [0.5, 1], normalised so that |field| <= 1 everywhere."""
-    out = np.zeros_like(x)
+    xp = _xp(x)
+    out = xp.zeros_like(x)
     amps = rng.uniform(0.5, 1.0, nmodes)
     for m in range(nmodes):
         kx, ky, kz = rng.integers(1, 4, size=3)
         ph = rng.uniform(0.0, 2.0 * math.pi)
-        out += amps[m] * np.cos(2 * math.pi * (kx * x / L[0] + ky * y / L[1] + kz * z / L[2]) + ph)
-    return out / amps.sum()
+        out = out + float(amps[m]) * xp.cos(
+            2 * math.pi * (float(kx) * x / L[0] + float(ky) * y / L[1] + float(kz) * z / L[2])
+            + float(ph))
+    return out / float(amps.sum())
 
 
 def state_iso_pert(xyz, spec: MeshSpec, seed=0, T=300.0, amp_rho=1e-3, amp_u=1.0):
@@ -156,7 +165,7 @@ def state_iso_rest(xyz, spec: MeshSpec, T=300.0):
     """Isothermal hydrostatic state at rest (discretely well balanced)."""
     z = xyz[:, 2]
     rho, p = isothermal(z, T, gas_R=spec.gas_R, grav=spec.grav)
-    zero = np.zeros_like(z)
+    zero = _xp(z).zeros_like(z)
     return _pack(rho, zero, zero, zero, p, z, spec.gamma, spec.grav)
 
 
@@ -168,23 +177,27 @@ def state_bubble(xyz, spec: MeshSpec, seed: Optional[int] = None, theta0=300.0, 
     (+-50 m) and the amplitude (x [0.8, 1.2])."""
     if seed is not None:
         rng = np.random.default_rng(seed)
-        centre = tuple(c + rng.uniform(-50.0, 50.0) for c in centre)
-        amp = amp * rng.uniform(0.8, 1.2)
+        centre = tuple(c + float(rng.uniform(-50.0, 50.0)) for c in centre)
+        amp = amp * float(rng.uniform(0.8, 1.2))
+    xp = _xp(xyz)
     x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
     pi, p = neutral(z, theta0, gas_R=spec.gas_R, grav=spec.grav, gamma=spec.gamma)
-    r = np.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2)
-    dth = np.where(r <= rc, amp * 0.5 * (1.0 + np.cos(math.pi * np.minimum(r, rc) / rc)), 0.0)
+    r = xp.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2)
+    rcl = xp.clip(r, None, rc) if xp is np else r.clamp(max=rc)
+    dth = amp * 0.5 * (1.0 + xp.cos(math.pi * rcl / rc))
+    dth = dth * (r <= rc)
     rho = p / (spec.gas_R * (theta0 + dth) * pi)
-    zero = np.zeros_like(z)
+    zero = xp.zeros_like(z)
     return _pack(rho, zero, zero, zero, p, z, spec.gamma, spec.grav)
 
 
 def channel_background(y, z, spec: MeshSpec, T0=300.0, dT=15.0):
     """Per-column isothermal hydrostatic background with
     T(y) = T0 - dT/2 (1 - cos(pi y/Ly)); returns (T, rho, p)."""
+    xp = _xp(y)
     Ly = spec.hi[1] - spec.lo[1]
-    T = T0 - 0.5 * dT * (1.0 - np.cos(math.pi * (y - spec.lo[1]) / Ly))
-    p = P0 * np.exp(-spec.grav * z / (spec.gas_R * T))
+    T = T0 - 0.5 * dT * (1.0 - xp.cos(math.pi * (y - spec.lo[1]) / Ly))
+    p = P0 * xp.exp(-spec.grav * z / (spec.gas_R * T))
     return T, p / (spec.gas_R * T), p
 
 
@@ -193,17 +206,18 @@ def state_channel(xyz, spec: MeshSpec, seed=0, T0=300.0, dT=15.0, bump=1.0, sigm
     background: f u = -g z T'(y)/T(y), zero at the walls, about 40 m/s at the
     top; plus a seeded Gaussian zonal-wind bump of `bump` m/s, width sigma."""
     rng = np.random.default_rng(seed)
+    xp = _xp(xyz)
     x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
     Ly = spec.hi[1] - spec.lo[1]
     Lx = spec.hi[0] - spec.lo[0]
     T, rho, p = channel_background(y, z, spec, T0, dT)
-    dTdy = -0.5 * dT * (math.pi / Ly) * np.sin(math.pi * (y - spec.lo[1]) / Ly)
+    dTdy = -0.5 * dT * (math.pi / Ly) * xp.sin(math.pi * (y - spec.lo[1]) / Ly)
     f = spec.coriolis_f if spec.coriolis_f != 0.0 else 1.0e-4
     u = -spec.grav * z * dTdy / (f * T)
-    xc = spec.lo[0] + rng.uniform(0.25, 0.75) * Lx
-    yc = spec.lo[1] + rng.uniform(0.35, 0.65) * Ly
-    u = u + bump * np.exp(-((x - xc) ** 2 + (y - yc) ** 2) / (2.0 * sigma ** 2))
-    zero = np.zeros_like(z)
+    xc = spec.lo[0] + float(rng.uniform(0.25, 0.75)) * Lx
+    yc = spec.lo[1] + float(rng.uniform(0.35, 0.65)) * Ly
+    u = u + bump * xp.exp(-((x - xc) ** 2 + (y - yc) ** 2) / (2.0 * sigma ** 2))
+    zero = xp.zeros_like(z)
     return _pack(rho, u, zero, zero, p, z, spec.gamma, spec.grav)
 
 

@@ -1,0 +1,67 @@
+"""Ensemble serving on the GPU: packed launches reproduce single-mesh
+stepping bit for bit, and every request's result is the same alone and in
+the mix (FP64 and FP32-mixed members; bitwise, the tolerance is 0)."""
+import numpy as np
+import pytest
+
+from paper_2605_16684_amd import serving as S
+from paper_2605_16684_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_packed_steps_equal_single_mesh_steps():
+    from paper_2605_16684_amd import esdg
+    reqs = [S.Request(0, "bubble", (3, 2, 4), 4, S.FP64, 1, 3),
+            S.Request(1, "channel", (5, 3, 2), 4, S.FP64, 2, 3),
+            S.Request(2, "bubble", (2, 2, 2), 4, S.FP64, 3, 3)]
+    members, ref = [], []
+    for r in reqs:
+        m, q, _ = S._make_member_mesh(r)
+        dt = m.cfl_dt(q, 0.5)
+        members.append((m, q.clone(), torch.empty_like(q), torch.zeros_like(q), dt))
+        qa, dqa = q.clone(), torch.zeros_like(q)
+        for _ in range(3):
+            m.lsrk_step(qa, dqa, dt)
+        ref.append(qa)
+    pack = esdg.Pack()
+    pack.set_members([x[0] for x in members], [x[1] for x in members], [x[2] for x in members],
+                     [x[3] for x in members], [x[4] for x in members], [0, 0, 0])
+    pack.step(3)
+    torch.cuda.synchronize()
+    for (m, q0, q1, dq, dt), qa in zip(members, ref):
+        assert torch.equal(q1, qa)        # 3 steps: state is in buffer 0 ^ 1
+    pack.close()
+
+
+def test_alone_and_in_the_mix_give_identical_results(tmp_path):
+    tuner = S.Autotuner(str(tmp_path / "epw.json"), target_nodes=1.5e5)
+    reqs = S.request_stream(n=8, seed=7, mean_interarrival=2e-3, steps=4, kmin=2, kmax=5,
+                            orders=(3, 4))
+    budget = int(0.5 * sum(S.footprint_bytes(r) for r in reqs))
+    budget = max(budget, max(S.footprint_bytes(r) for r in reqs))
+    ex = S.GpuExecutor(tuner, keep_results=True)
+    srv = S.Server(budget, executor=ex)
+    st = srv.run(reqs)
+    print("[serving mix]", st.as_dict(), flush=True)
+    assert st.n_completed == len(reqs)
+    assert st.max_concurrent_members > 1
+    for r in reqs:
+        alone = S.Server(10 * S.footprint_bytes(r), executor=S.GpuExecutor(tuner, keep_results=True))
+        r1 = S.Request(r.rid, r.kind, r.K, r.N, r.precision, r.seed, r.steps, 0.0)
+        alone.run([r1])
+        a, b = srv.results[r.rid], alone.results[r.rid]
+        assert a.shape == b.shape
+        assert np.array_equal(a, b), (r, np.abs(a - b).max())
+        assert np.all(np.isfinite(a))
+
+
+def test_autotuner_caches_a_compiled_choice(tmp_path):
+    from paper_2605_16684_amd import esdg
+    path = tmp_path / "t.json"
+    t = S.Autotuner(str(path), target_nodes=1e5)
+    e = t.epw(4, S.FP64)
+    assert e in esdg.epw_options(4, S.FP64)
+    t2 = S.Autotuner(str(path))
+    assert t2.table["N4_fp64"]["epw"] == e

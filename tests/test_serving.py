@@ -1,0 +1,103 @@
+"""Scheduler of the ensemble server on the CPU fake executor: admission by
+HBM footprint (with backfill), continuous batching, eviction, statistics,
+failure isolation."""
+import numpy as np
+import pytest
+
+from paper_2605_16684_amd import serving as S
+
+
+def _reqs(n=12, seed=1, steps=5, mean=1e-3):
+    return S.request_stream(n=n, seed=seed, mean_interarrival=mean, steps=steps, kmin=2, kmax=6)
+
+
+def test_request_stream_shape():
+    rs = S.request_stream(n=400, seed=3, mean_interarrival=0.02)
+    assert len(rs) == 400
+    assert all(8 <= k <= 40 for r in rs for k in r.K)
+    assert {r.N for r in rs} == {3, 4, 5, 7}
+    assert {r.precision for r in rs} == {S.FP64, S.FP32_MIXED}
+    assert {r.kind for r in rs} == {"bubble", "channel"}
+    gaps = np.diff([0.0] + [r.arrival for r in rs])
+    assert abs(gaps.mean() - 0.02) < 0.004          # Poisson arrivals, mean 0.02 s
+    assert [r.seed for r in rs] == list(range(400))
+    assert S.request_stream(n=5, seed=3) == S.request_stream(n=5, seed=3)
+
+
+def test_all_requests_complete_and_budget_holds():
+    rs = _reqs()
+    budget = int(2.5 * max(S.footprint_bytes(r) for r in rs))
+    srv = S.Server(budget, executor=S.FakeExecutor())
+    st = srv.run(rs, realtime=False)
+    assert st.n_completed == len(rs) and st.n_rejected == 0
+    assert st.peak_footprint_bytes <= budget
+    for r in rs:
+        mb = srv.members[r.rid]
+        assert mb.steps_done == r.steps and len(mb.latencies) == r.steps
+        assert all(x > 0 for x in mb.latencies)
+        assert mb.admitted >= r.arrival - 1e-12
+
+
+def test_admission_binds_and_members_overlap():
+    rs = _reqs(n=20, mean=1e-5)                       # burst: everyone arrives at once
+    total = sum(S.footprint_bytes(r) for r in rs)
+    srv = S.Server(total // 3, executor=S.FakeExecutor())
+    st = srv.run(rs, realtime=False)
+    assert st.n_completed == 20
+    assert 1 < st.max_concurrent_members < 20         # batched, but not all at once
+    assert st.queue_wait_p99_ms > 0
+    # several (N, precision) buckets ran in the same rounds
+    assert st.buckets_seen >= 2
+
+
+def test_backfill_small_requests_pass_a_blocked_large_one():
+    big = S.Request(0, "bubble", (7, 7, 7), 7, S.FP64, 0, 3, 0.0)
+    small = [S.Request(i, "bubble", (2, 2, 2), 3, S.FP64, i, 3, 1e-6 * i) for i in range(1, 5)]
+    blocker = S.Request(9, "channel", (8, 8, 7), 7, S.FP64, 9, 40, 0.0)
+    budget = S.footprint_bytes(blocker) + S.footprint_bytes(small[0]) * 4 + 1
+    srv = S.Server(budget, executor=S.FakeExecutor())
+    srv.run([blocker, big] + small, realtime=False)
+    # the small requests were admitted while the big one still waited for the blocker
+    assert max(srv.members[r.rid].admitted for r in small) < srv.members[0].admitted
+
+
+def test_requests_larger_than_budget_are_rejected_not_hung():
+    rs = _reqs(n=4)
+    huge = S.Request(99, "bubble", (40, 40, 40), 7, S.FP64, 99, 2, 0.0)
+    budget = 4 * max(S.footprint_bytes(r) for r in rs)
+    st = S.Server(budget, executor=S.FakeExecutor()).run(rs + [huge], realtime=False)
+    assert st.n_rejected == 1 and st.n_completed == 4
+
+
+def test_failure_isolation():
+    rs = _reqs(n=8)
+    ex = S.FakeExecutor(fail_on={3})
+    srv = S.Server(10 * max(S.footprint_bytes(r) for r in rs), executor=ex)
+    st = srv.run(rs, realtime=False)
+    assert st.n_rejected == 1 and st.n_completed == 7
+    assert 3 not in srv.members
+
+
+def test_statistics_are_computed_from_member_steps():
+    rs = _reqs(n=6, steps=4)
+    srv = S.Server(10 * max(S.footprint_bytes(r) for r in rs), executor=S.FakeExecutor())
+    st = srv.run(rs, realtime=False)
+    lat = np.array([x for r in rs for x in srv.members[r.rid].latencies])
+    assert st.step_latency_p50_ms == pytest.approx(np.percentile(lat, 50) * 1e3)
+    assert st.step_latency_p99_ms == pytest.approx(np.percentile(lat, 99) * 1e3)
+    work = sum(r.nodes * 5 * r.steps for r in rs)
+    assert st.aggregate_dof_rhs_per_s == pytest.approx(work / st.makespan_s)
+    # fake cost model: a lone member's step latency is overhead + nodes * cost
+    ex = S.FakeExecutor()
+    one = S.Request(0, "bubble", (3, 3, 3), 4, S.FP64, 0, 3, 0.0)
+    srv1 = S.Server(10 * S.footprint_bytes(one), executor=ex)
+    srv1.run([one], realtime=False)
+    lats = srv1.members[0].latencies
+    assert lats[1] == pytest.approx(ex.overhead + one.nodes * ex.cost(4, S.FP64))
+
+
+def test_footprint_formula():
+    r = S.Request(0, "bubble", (10, 10, 10), 4, S.FP64, 0, 1)
+    assert S.footprint_bytes(r) >= 120 * r.nodes
+    rm = S.Request(0, "bubble", (10, 10, 10), 4, S.FP32_MIXED, 0, 1)
+    assert S.footprint_bytes(rm) - S.footprint_bytes(r) == 20 * r.nodes
