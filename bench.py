@@ -204,8 +204,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the mesh would shard by element slabs with face-trace exchange; see DESIGN.md)",
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(a mesh would shard into element slabs that exchange face traces every stage)",
               file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:

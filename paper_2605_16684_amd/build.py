@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "esdg_api.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "esdg_device.hpp"), os.path.join(ROOT, "include", "esdg.h")]
+DEPS = [SRC, os.path.join(HERE, "csrc", "esdg_device.hpp"), os.path.join(HERE, "csrc", "esdg_mixed.hpp"),
+        os.path.join(ROOT, "include", "esdg.h")]
 LIB = os.path.join(HERE, "libesdg.so")
 ARCH = "gfx950"
 
