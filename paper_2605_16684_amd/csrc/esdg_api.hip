@@ -314,6 +314,7 @@ StageParams base_params(const esdg_mesh *m)
     P.zlo = m->desc.lo[2];
     P.zhi = m->desc.hi[2];
     P.gamma = m->desc.gamma;
+    P.gm1i = 1.0 / (m->desc.gamma - 1.0);
     P.grav = m->desc.grav;
     P.cor_f = m->desc.coriolis_f;
     P.lnz_scale = m->desc.gas_R * 300.0;

@@ -60,7 +60,7 @@ struct StageParams {
     int periodic[3];
     double two_h[3];  // 2 / h_r
     double zlo, zhi;  // box extent in z (geopotential)
-    double gamma, grav, cor_f;
+    double gamma, gm1i, grav, cor_f;  // gm1i = 1 / (gamma - 1)
     double lnz_scale;  // ln(z/z_s) = ln(z * lnz_scale), z_s = 1/(R * 300 K)
     double A, B, dt;   // LSRK stage coefficients
     int mode, mask, surf, nblocks;
@@ -75,6 +75,34 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     const int per = nb >> 3, rem = nb & 7;
     const int x = b & 7, i = b >> 3;
     return x * per + (x < rem ? x : rem) + i;
+}
+
+// Element coordinates (ex, ey, ez) of element e (meshes hold < 2^31 elements).
+__device__ __forceinline__ void elem_coords(const StageParams &P, int64_t e, int ec[3])
+{
+    const unsigned u = (unsigned)e;
+    const unsigned kx = (unsigned)P.K[0], ky = (unsigned)P.K[1];
+    const unsigned t = u / kx;
+    ec[0] = (int)(u - t * kx);
+    ec[1] = (int)(t % ky);
+    ec[2] = (int)(t / ky);
+}
+
+// Square root of a positive normal number: hardware reciprocal square-root
+// estimate refined by Goldschmidt's iteration with two residual corrections
+// (the scheme of the IEEE sequence without its range scaling and
+// special-value handling, which positive normal operands do not need).
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
 }
 
 // Per-node quantities of one line, held in registers: density, half
@@ -169,6 +197,37 @@ __device__ __forceinline__ double sym_flux(const Node &a, const Node &b, double 
     return rho_ln;
 }
 
+// sym_flux for a pair whose two log-means both take the series branch (the
+// caller has checked the whole line): no branch selects, and the 1/2 of the
+// mean folded into the series coefficients.
+constexpr double H1 = 0.5 * S1, H2 = 0.5 * S2, H3 = 0.5 * S3;
+
+template <int R>
+__device__ __forceinline__ double sym_flux_series(const Node &a, const Node &b, double phi_m,
+                                                  double gm1i, double S[5])
+{
+    const double dr = b.r - a.r, sr = a.r + b.r;
+    const double xr = dr * frcp(sr);
+    const double ur = xr * xr;
+    const double rho_ln = sr * (0.5 - ur * (H1 + ur * (H2 + ur * H3)));
+    const double dz = b.z - a.z, sz = a.z + b.z;
+    const double rz = frcp(sz);
+    const double fz = dz * rz;
+    const double uz = fz * fz;
+    const double izln = (rz + rz) * (1.0 + uz * (I1 + uz * (I2 + uz * I3)));
+    const double hRa = hcomp<R>(a), hRb = hcomp<R>(b);
+    const double frho = rho_ln * (hRa + hRb);
+    S[0] = frho;
+    S[1] = frho * (a.h0 + b.h0);
+    S[2] = frho * (a.h1 + b.h1);
+    S[3] = frho * (a.h2 + b.h2);
+    S[1 + R] += a.hp + b.hp;
+    const double hh = a.h0 * b.h0 + a.h1 * b.h1 + a.h2 * b.h2;
+    const double cross = a.hp * hRb + b.hp * hRa;
+    S[4] = frho * (izln * gm1i + 2.0 * hh + phi_m) + 2.0 * cross;
+    return rho_ln;
+}
+
 struct Cons {
     double v[5];
 };
@@ -208,7 +267,7 @@ __device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const C
                                           double phi, double s, const StageParams &P,
                                           double Fn[5])
 {
-    const double g = P.gamma, gm1 = g - 1.0, gm1i = 1.0 / gm1;
+    const double g = P.gamma, gm1 = g - 1.0, gm1i = P.gm1i;
     const Node b = primitives(qp, phi, gm1);
     double rho_ln, izln;
     {
@@ -246,8 +305,8 @@ __device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const C
     S[4] = frho * (izln * gm1i + 2.0 * hh + phi) + 2.0 * cross;
     double hl = 0.0;
     if (P.surf == 0) {
-        const double la = 2.0 * fabs(hRa) + sqrt(g * a.zi);
-        const double lb = 2.0 * fabs(hRb) + sqrt(g * b.zi);
+        const double la = 2.0 * fabs(hRa) + sqrt_pos(g * a.zi);
+        const double lb = 2.0 * fabs(hRb) + sqrt_pos(g * b.zi);
         hl = 0.5 * (la > lb ? la : lb);
     }
 #pragma unroll
@@ -288,10 +347,12 @@ __device__ __forceinline__ void plus_state(const StageParams &P, int m, const in
     }
 }
 
-// Per-node logarithms of one line, computed only when some pair of the line
-// can reach the log branch (the extreme pair maximises |b-a|/(b+a)).
+// Whether some pair of a line can reach the log branch of the log-mean: the
+// extreme pair maximises |b-a|/(b+a).  The test is slightly tighter than the
+// branch rule, so that a line declared log-free never has a pair whose own
+// test selects the log branch.
 template <int NQ>
-__device__ __forceinline__ void line_logs(const double x[NQ], double scale, double lx[NQ])
+__device__ __forceinline__ bool line_spread(const double x[NQ])
 {
     double mn = x[0], mx = x[0];
 #pragma unroll
@@ -299,7 +360,16 @@ __device__ __forceinline__ void line_logs(const double x[NQ], double scale, doub
         mn = fmin(mn, x[t]);
         mx = fmax(mx, x[t]);
     }
-    if (mx - mn >= LM_SQRT_EPS_LINE * (mx + mn)) {
+    return !(mx - mn < LM_SQRT_EPS_LINE * (mx + mn));
+}
+
+// Per-node logarithms of one line, only where the line can reach the log
+// branch.
+template <int NQ>
+__device__ __forceinline__ void line_logs(const double x[NQ], bool need, double scale,
+                                          double lx[NQ])
+{
+    if (need) {
 #pragma unroll
         for (int t = 0; t < NQ; ++t) lx[t] = log(x[t] * scale);
     } else {
@@ -308,24 +378,41 @@ __device__ __forceinline__ void line_logs(const double x[NQ], double scale, doub
     }
 }
 
-// Volume pairs and face terms of one line in direction R; acc receives the
-// unscaled sums (the caller multiplies by 2/h_R); qv receives the line's
-// conservative states (the z phase reuses them for the update).
+// Accumulates the shares of one pair (a, b) of an R-line.
+template <int NQ, int R>
+__device__ __forceinline__ void pair_shares(const OrderTables &tb, const Node nd[NQ],
+                                            const double phi_k[NQ], int a, int b,
+                                            const double S[5], double rho_ln, double acc[NQ][5])
+{
+    const double tab = tb.T[a][b], tba = tb.T[b][a];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        acc[a][v] -= tab * S[v];
+        acc[b][v] -= tba * S[v];
+    }
+    if (R == 2) {
+        // gravity term G_ab = rho_hat [[phi]]/2, rho_hat = {{b}} {{rho}}_log / b_a,
+        // b = z/2; partner: G_ba = -G_ab z_a / z_b
+        const double X = 0.25 * rho_ln * (nd[a].z + nd[b].z) * (phi_k[b] - phi_k[a]);
+        acc[a][3] -= tab * (X * nd[a].zi);
+        acc[b][3] += tba * (X * nd[b].zi);
+    }
+}
+
+// Face terms and volume pairs of one line in direction R; acc receives the
+// unscaled sums (the caller multiplies by 2/h_R).  The face terms come
+// first, so that the line's conservative states and the neighbours' die
+// before the pair loop, which holds only the primitives and the sums.
 template <int NQ, int R>
 __device__ __forceinline__ void line_terms(const StageParams &P, const OrderTables &tb, int m,
                                            int64_t e, const int ec[3], const double phi_k[NQ],
-                                           double acc[NQ][5], double qv[NQ][5])
+                                           double acc[NQ][5])
 {
     constexpr int NQ3 = NQ * NQ * NQ;
-    const double gm1 = P.gamma - 1.0, gm1i = 1.0 / gm1;
+    const double gm1 = P.gamma - 1.0, gm1i = P.gm1i;
     const double *__restrict__ qin = P.q_in;
-#pragma unroll
-    for (int a = 0; a < NQ; ++a)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) acc[a][v] = 0.0;
 
-    // the line's own states, then the face neighbours' (their latency hides
-    // behind the pair loop)
+    // the line's own states, then the face neighbours'
     Cons qc[NQ];
 #pragma unroll
     for (int t = 0; t < NQ; ++t) load_cons(qin, e, NQ3, line_node<NQ, R>(m, t), qc[t]);
@@ -354,43 +441,10 @@ __device__ __forceinline__ void line_terms(const StageParams &P, const OrderTabl
 #pragma unroll
     for (int t = 0; t < NQ; ++t) nd[t] = primitives(qc[t], R == 2 ? phi_k[t] : phi_k[0], gm1);
 
-    if (P.mask & TERM_VOL) {
-        double lr[NQ], lz[NQ];
-        {
-            double xr[NQ], xz[NQ];
 #pragma unroll
-            for (int t = 0; t < NQ; ++t) {
-                xr[t] = nd[t].r;
-                xz[t] = nd[t].z;
-            }
-            line_logs<NQ>(xr, 1.0, lr);
-            line_logs<NQ>(xz, P.lnz_scale, lz);
-        }
+    for (int a = 0; a < NQ; ++a)
 #pragma unroll
-        for (int a = 0; a < NQ; ++a) {
-#pragma unroll
-            for (int b = a + 1; b < NQ; ++b) {
-                const double phi_m = R == 2 ? 0.5 * (phi_k[a] + phi_k[b]) : phi_k[0];
-                double S[5];
-                const double rho_ln =
-                    sym_flux<R>(nd[a], nd[b], lr[a], lr[b], lz[a], lz[b], phi_m, gm1i, S);
-                const double tab = tb.T[a][b], tba = tb.T[b][a];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    acc[a][v] -= tab * S[v];
-                    acc[b][v] -= tba * S[v];
-                }
-                if (R == 2) {
-                    // gravity term G_ab = rho_hat [[phi]]/2, rho_hat = {{b}} {{rho}}_log / b_a,
-                    // b = z/2; partner: G_ba = -G_ab z_a / z_b
-                    const double X = 0.25 * rho_ln * (nd[a].z + nd[b].z) * (phi_k[b] - phi_k[a]);
-                    acc[a][3] -= tab * (X * nd[a].zi);
-                    acc[b][3] += tba * (X * nd[b].zi);
-                }
-            }
-        }
-    }
-
+        for (int v = 0; v < 5; ++v) acc[a][v] = 0.0;
     if (faces) {
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
@@ -403,10 +457,46 @@ __device__ __forceinline__ void line_terms(const StageParams &P, const OrderTabl
             for (int v = 0; v < 5; ++v) acc[t][v] -= wi * Fn[v];
         }
     }
+
+    if (P.mask & TERM_VOL) {
+        double xr[NQ], xz[NQ];
 #pragma unroll
-    for (int t = 0; t < NQ; ++t)
+        for (int t = 0; t < NQ; ++t) {
+            xr[t] = nd[t].r;
+            xz[t] = nd[t].z;
+        }
+        const bool need_r = line_spread<NQ>(xr), need_z = line_spread<NQ>(xz);
+        // wave-uniform choice: the series-only loop when no line of the wave
+        // can reach the log branch
+        if (__ballot(need_r || need_z) == 0) {
+            // every pair of these lines takes the series branch of both log-means
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qv[t][v] = qc[t].v[v];
+            for (int a = 0; a < NQ; ++a) {
+#pragma unroll
+                for (int b = a + 1; b < NQ; ++b) {
+                    const double phi_m = R == 2 ? 0.5 * (phi_k[a] + phi_k[b]) : phi_k[0];
+                    double S[5];
+                    const double rho_ln = sym_flux_series<R>(nd[a], nd[b], phi_m, gm1i, S);
+                    pair_shares<NQ, R>(tb, nd, phi_k, a, b, S, rho_ln, acc);
+                }
+            }
+        } else {
+            double lr[NQ], lz[NQ];
+            line_logs<NQ>(xr, need_r, 1.0, lr);
+            line_logs<NQ>(xz, need_z, P.lnz_scale, lz);
+#pragma unroll
+            for (int a = 0; a < NQ; ++a) {
+#pragma unroll
+                for (int b = a + 1; b < NQ; ++b) {
+                    const double phi_m = R == 2 ? 0.5 * (phi_k[a] + phi_k[b]) : phi_k[0];
+                    double S[5];
+                    const double rho_ln =
+                        sym_flux<R>(nd[a], nd[b], lr[a], lr[b], lz[a], lz[b], phi_m, gm1i, S);
+                    pair_shares<NQ, R>(tb, nd, phi_k, a, b, S, rho_ln, acc);
+                }
+            }
+        }
+    }
 }
 
 template <int NQ, int EPW>
@@ -433,10 +523,7 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
 
     int ec[3] = {0, 0, 0};
     if (act) {
-        ec[0] = (int)(e % P.K[0]);
-        const int64_t t = e / P.K[0];
-        ec[1] = (int)(t % P.K[1]);
-        ec[2] = (int)(t / P.K[1]);
+        elem_coords(P, e, ec);
     }
     // geopotential at the nodes of this element's z-levels
     double phi_k[NQ];
@@ -451,8 +538,24 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
         }
     }
 
-    double acc[NQ][5], qv[NQ][5];
+    double acc[NQ][5];
     const bool vol_or_face = (P.mask & (TERM_VOL | TERM_FACE)) != 0;
+
+    // dq of the nodes this lane finishes in the z phase, fetched now so that
+    // its latency hides behind the three phases (up to N = 4; higher orders
+    // have no registers to spare and fetch it in the finish)
+    constexpr bool early_dq = MODE == MODE_STAGE && NQ <= 5;
+    // the first LSRK stage (A = 0) does not read dq at all
+    const bool use_dq = MODE == MODE_STAGE && P.A != 0.0;
+    const int64_t base0 = e * 5 * NQ3 + m;
+    double dv[NQ][5];
+    if (early_dq && act && use_dq) {
+        const double *__restrict__ dqr = P.dq;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) dv[t][v] = dqr[base0 + v * NQ3 + NQ2 * t];
+    }
 
     // x phase: lane m = (j, k)
     if (act) {
@@ -460,7 +563,7 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
             double phl[NQ];
 #pragma unroll
             for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
-            line_terms<NQ, 0>(P, tb, m, e, ec, phl, acc, qv);
+            line_terms<NQ, 0>(P, tb, m, e, ec, phl, acc);
         } else {
 #pragma unroll
             for (int t = 0; t < NQ; ++t)
@@ -481,7 +584,7 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
         double phl[NQ];
 #pragma unroll
         for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
-        line_terms<NQ, 1>(P, tb, m, e, ec, phl, acc, qv);
+        line_terms<NQ, 1>(P, tb, m, e, ec, phl, acc);
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             const int n = line_node<NQ, 1>(m, t);
@@ -495,23 +598,22 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     if (!act) return;
     const bool src = (P.mask & TERM_SRC) != 0;
     if (vol_or_face) {
-        line_terms<NQ, 2>(P, tb, m, e, ec, phi_k, acc, qv);
+        line_terms<NQ, 2>(P, tb, m, e, ec, phi_k, acc);
     } else {
-        const double *__restrict__ qin = P.q_in;
 #pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-            Cons c;
-            load_cons(qin, e, NQ3, m + NQ2 * t, c);
+        for (int t = 0; t < NQ; ++t)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                acc[t][v] = 0.0;
-                qv[t][v] = c.v[v];
-            }
-        }
+            for (int v = 0; v < 5; ++v) acc[t][v] = 0.0;
     }
-    // finish: the state arrays never overlap (checked on the host), so the
-    // loads of dq are issued together before the first store
-    const int64_t base0 = e * 5 * NQ3 + m;
+    // finish: the z line's states again (cached: this phase has just read
+    // them).  The state arrays never overlap (checked on the host), so all
+    // loads are issued before the first store.
+    const double *__restrict__ qin = P.q_in;
+    double qv[NQ][5];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
     if (MODE == MODE_RHS) {
         double *__restrict__ rout = P.r_out;
 #pragma unroll
@@ -530,11 +632,12 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     } else {
         double *__restrict__ dqp = P.dq;
         double *__restrict__ qout = P.q_out;
-        double dv[NQ][5];
+        if (!early_dq && use_dq) {
 #pragma unroll
-        for (int t = 0; t < NQ; ++t)
+            for (int t = 0; t < NQ; ++t)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) dv[t][v] = dqp[base0 + v * NQ3 + NQ2 * t];
+                for (int v = 0; v < 5; ++v) dv[t][v] = dqp[base0 + v * NQ3 + NQ2 * t];
+        }
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             const int n = m + NQ2 * t;
@@ -547,7 +650,7 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double d = P.A * dv[t][v] + P.dt * Rv[v];
+                const double d = use_dq ? P.A * dv[t][v] + P.dt * Rv[v] : P.dt * Rv[v];
                 dqp[base0 + v * NQ3 + NQ2 * t] = d;
                 qout[base0 + v * NQ3 + NQ2 * t] = qv[t][v] + P.B * d;
             }

@@ -175,7 +175,7 @@ __device__ __forceinline__ void face_flux_mixed(const NodeF &a, const Cons &qm, 
                                                 float rr_f, float pr_f, float Fn[5])
 {
     const double gm1 = P.gamma - 1.0;
-    const float g = (float)P.gamma, gm1i = (float)(1.0 / gm1);
+    const float g = (float)P.gamma, gm1i = (float)P.gm1i;
     const float zscale = (float)P.lnz_scale;
     const NodeF b = primitives_mixed(qp, phi, gm1, rr_f, pr_f, zscale);
     const float rho_ln = log_mean_f(a.r, b.r, a.lr, b.lr);
@@ -219,7 +219,7 @@ __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const Ord
     constexpr int NQ3 = NQ * NQ * NQ;
     const StageParams &P = M.s;
     const double gm1 = P.gamma - 1.0;
-    const float gm1i = (float)(1.0 / gm1);
+    const float gm1i = (float)P.gm1i;
     const float zscale = (float)P.lnz_scale;
     const double *__restrict__ qin = P.q_in;
 #pragma unroll
@@ -312,10 +312,7 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
 
     int ec[3] = {0, 0, 0};
     if (act) {
-        ec[0] = (int)(e % P.K[0]);
-        const int64_t t = e / P.K[0];
-        ec[1] = (int)(t % P.K[1]);
-        ec[2] = (int)(t / P.K[1]);
+        elem_coords(P, e, ec);
     }
     double phi_k[NQ];
     {
@@ -414,11 +411,15 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
     } else {
         double *__restrict__ dqp = P.dq;
         double *__restrict__ qout = P.q_out;
+        // the first LSRK stage (A = 0) does not read dq
+        const bool use_dq = P.A != 0.0;
         double dv[NQ][5];
+        if (use_dq) {
 #pragma unroll
-        for (int t = 0; t < NQ; ++t)
+            for (int t = 0; t < NQ; ++t)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) dv[t][v] = dqp[base0 + v * NQ3 + NQ2 * t];
+                for (int v = 0; v < 5; ++v) dv[t][v] = dqp[base0 + v * NQ3 + NQ2 * t];
+        }
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             const int n = m + NQ2 * t;
@@ -433,7 +434,7 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double d = P.A * dv[t][v] + P.dt * Rv[v];
+                const double d = use_dq ? P.A * dv[t][v] + P.dt * Rv[v] : P.dt * Rv[v];
                 dqp[base0 + v * NQ3 + NQ2 * t] = d;
                 qout[base0 + v * NQ3 + NQ2 * t] = qv[t][v] + P.B * d;
             }
