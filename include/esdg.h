@@ -44,8 +44,9 @@ extern "C" {
 
 enum {
     ESDG_OK = 0,
-    ESDG_EINVAL = -1,    /* bad argument: N outside 1..8, K < 1, hi <= lo,
-                            NULL/misaligned pointer, periodic z with grav != 0 */
+    ESDG_EINVAL = -1,    /* bad argument: N outside 1..8, K < 1, K[0]K[1]K[2] >= 2^31,
+                            hi <= lo, NULL/misaligned pointer, periodic z with
+                            grav != 0, no compiled kernel variant */
     ESDG_ENOMEM = -2,    /* device allocation failed */
     ESDG_EHIP = -3,      /* HIP runtime error; the message carries its text */
     ESDG_ENONPHYS = -4,  /* rho <= 0, p <= 0 or NaN met in a state */

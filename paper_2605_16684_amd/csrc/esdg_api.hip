@@ -301,6 +301,17 @@ GeomParams geom(const esdg_mesh *m)
     return G;
 }
 
+// Traversal bricks (elements): y and z neighbours of an element are visited
+// within about one brick of it.  Bricks of 32 x 4 x 4 elements up to N = 4
+// and 8 x 4 x 4 above (larger elements, fewer of them in flight per XCD)
+// measured best on the bubble and channel workloads.
+void traversal_tiles(const esdg_mesh *m, int tile[3])
+{
+    tile[0] = std::min(m->desc.K[0], m->N <= 4 ? 32 : 8);
+    tile[1] = std::min(m->desc.K[1], 4);
+    tile[2] = std::min(m->desc.K[2], 4);
+}
+
 StageParams base_params(const esdg_mesh *m)
 {
     StageParams P;
@@ -321,6 +332,7 @@ StageParams base_params(const esdg_mesh *m)
     P.surf = m->desc.surface_flux;
     P.flag = m->d_flag;
     P.mask = TERM_VOL | TERM_FACE | TERM_SRC;
+    traversal_tiles(m, P.tile);
     return P;
 }
 
@@ -524,6 +536,8 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         if (d->K[k] < 1) return fail(ESDG_EINVAL, "K[%d]=%d < 1", k, d->K[k]);
         if (!(d->hi[k] > d->lo[k])) return fail(ESDG_EINVAL, "hi[%d] <= lo[%d]", k, k);
     }
+    if ((int64_t)d->K[0] * d->K[1] * d->K[2] >= ((int64_t)1 << 31))
+        return fail(ESDG_EINVAL, "K[0]*K[1]*K[2] must be below 2^31 elements");
     if (d->periodic[2] && d->grav != 0.0)
         return fail(ESDG_EINVAL, "periodic z with grav != 0 (phi = g z is not periodic)");
     if (!(d->gamma > 1.0) || !(d->gas_R > 0.0))

@@ -64,6 +64,7 @@ struct StageParams {
     double lnz_scale;  // ln(z/z_s) = ln(z * lnz_scale), z_s = 1/(R * 300 K)
     double A, B, dt;   // LSRK stage coefficients
     int mode, mask, surf, nblocks;
+    int tile[3];  // traversal bricks of tile[0] x tile[1] x tile[2] elements
 };
 
 // Blocks are dealt to the 8 XCDs round-robin by block id.  Remap so that each
@@ -77,15 +78,33 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * per + (x < rem ? x : rem) + i;
 }
 
-// Element coordinates (ex, ey, ez) of element e (meshes hold < 2^31 elements).
-__device__ __forceinline__ void elem_coords(const StageParams &P, int64_t e, int ec[3])
+// Element visited at traversal position i.  The mesh is walked in bricks
+// of tile[0] x tile[1] x tile[2] elements (x fastest inside a brick; bricks
+// by x, then y, then z; partial bricks at the far ends), so that the y and z
+// neighbours of an element are visited shortly before or after it and their
+// face traces are still in L2.  Bricks of the whole mesh give the plain
+// x-fastest order.  Returns the storage index; ec receives (ex, ey, ez).
+__device__ __forceinline__ int64_t tile_element(const StageParams &P, int64_t i, int ec[3])
 {
-    const unsigned u = (unsigned)e;
-    const unsigned kx = (unsigned)P.K[0], ky = (unsigned)P.K[1];
-    const unsigned t = u / kx;
-    ec[0] = (int)(u - t * kx);
-    ec[1] = (int)(t % ky);
-    ec[2] = (int)(t / ky);
+    const unsigned u = (unsigned)i;
+    const unsigned kx = P.K[0], ky = P.K[1], kz = P.K[2];
+    const unsigned tx = P.tile[0], ty = P.tile[1], tz = P.tile[2];
+    const unsigned slab = kx * ky * tz;
+    const unsigned s = u / slab, r0 = u - s * slab;
+    const unsigned nz = min(tz, kz - s * tz);
+    const unsigned band = kx * ty * nz;
+    const unsigned b = r0 / band, r1 = r0 - b * band;
+    const unsigned ny = min(ty, ky - b * ty);
+    const unsigned brick = tx * ny * nz;
+    const unsigned c = r1 / brick, r2 = r1 - c * brick;
+    const unsigned nx = min(tx, kx - c * tx);
+    const unsigned plane = nx * ny;
+    const unsigned zl = r2 / plane, r3 = r2 - zl * plane;
+    const unsigned yl = r3 / nx, xl = r3 - yl * nx;
+    ec[0] = (int)(c * tx + xl);
+    ec[1] = (int)(b * ty + yl);
+    ec[2] = (int)(s * tz + zl);
+    return (int64_t)ec[0] + (int64_t)kx * (ec[1] + (int64_t)ky * ec[2]);
 }
 
 // Square root of a positive normal number: hardware reciprocal square-root
@@ -403,10 +422,10 @@ __device__ __forceinline__ void pair_shares(const OrderTables &tb, const Node nd
 // unscaled sums (the caller multiplies by 2/h_R).  The face terms come
 // first, so that the line's conservative states and the neighbours' die
 // before the pair loop, which holds only the primitives and the sums.
-template <int NQ, int R>
+template <int NQ, int R, bool KEEP = false>
 __device__ __forceinline__ void line_terms(const StageParams &P, const OrderTables &tb, int m,
                                            int64_t e, const int ec[3], const double phi_k[NQ],
-                                           double acc[NQ][5])
+                                           double acc[NQ][5], double (*qkeep)[5] = nullptr)
 {
     constexpr int NQ3 = NQ * NQ * NQ;
     const double gm1 = P.gamma - 1.0, gm1i = P.gm1i;
@@ -435,6 +454,13 @@ __device__ __forceinline__ void line_terms(const StageParams &P, const OrderTabl
                 qp[side].v[1 + R] = -qp[side].v[1 + R];
             }
         }
+    }
+
+    if (KEEP) {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qkeep[t][v] = qc[t].v[v];
     }
 
     Node nd[NQ];
@@ -518,13 +544,12 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     const int tid = threadIdx.x;
     const int el = tid / NQ2;
     const int m = tid - el * NQ2;
-    const int64_t e = (int64_t)lb * EPW + el;
-    const bool act = (el < EPW) && (e < P.ne);
+    const int64_t it = (int64_t)lb * EPW + el;  // traversal position
+    const bool act = (el < EPW) && (it < P.ne);
 
     int ec[3] = {0, 0, 0};
-    if (act) {
-        elem_coords(P, e, ec);
-    }
+    int64_t e = 0;
+    if (act) e = tile_element(P, it, ec);
     // geopotential at the nodes of this element's z-levels
     double phi_k[NQ];
     {
@@ -541,21 +566,7 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     double acc[NQ][5];
     const bool vol_or_face = (P.mask & (TERM_VOL | TERM_FACE)) != 0;
 
-    // dq of the nodes this lane finishes in the z phase, fetched now so that
-    // its latency hides behind the three phases (up to N = 4; higher orders
-    // have no registers to spare and fetch it in the finish)
-    constexpr bool early_dq = MODE == MODE_STAGE && NQ <= 5;
-    // the first LSRK stage (A = 0) does not read dq at all
-    const bool use_dq = MODE == MODE_STAGE && P.A != 0.0;
     const int64_t base0 = e * 5 * NQ3 + m;
-    double dv[NQ][5];
-    if (early_dq && act && use_dq) {
-        const double *__restrict__ dqr = P.dq;
-#pragma unroll
-        for (int t = 0; t < NQ; ++t)
-#pragma unroll
-            for (int v = 0; v < 5; ++v) dv[t][v] = dqr[base0 + v * NQ3 + NQ2 * t];
-    }
 
     // x phase: lane m = (j, k)
     if (act) {
@@ -597,23 +608,22 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     // z phase: lane m = (i, j) owns the nodes (i, j, 0..N) and finishes them
     if (!act) return;
     const bool src = (P.mask & TERM_SRC) != 0;
+    // the z line's states stay in registers for the update
+    double qv[NQ][5];
     if (vol_or_face) {
-        line_terms<NQ, 2>(P, tb, m, e, ec, phi_k, acc);
+        line_terms<NQ, 2, true>(P, tb, m, e, ec, phi_k, acc, qv);
     } else {
+        const double *__restrict__ qin = P.q_in;
 #pragma unroll
         for (int t = 0; t < NQ; ++t)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) acc[t][v] = 0.0;
+            for (int v = 0; v < 5; ++v) {
+                acc[t][v] = 0.0;
+                qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
+            }
     }
-    // finish: the z line's states again (cached: this phase has just read
-    // them).  The state arrays never overlap (checked on the host), so all
-    // loads are issued before the first store.
-    const double *__restrict__ qin = P.q_in;
-    double qv[NQ][5];
-#pragma unroll
-    for (int t = 0; t < NQ; ++t)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
+    // finish.  The state arrays never overlap (checked on the host), so the
+    // dq loads are issued before the first store.
     if (MODE == MODE_RHS) {
         double *__restrict__ rout = P.r_out;
 #pragma unroll
@@ -632,7 +642,10 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     } else {
         double *__restrict__ dqp = P.dq;
         double *__restrict__ qout = P.q_out;
-        if (!early_dq && use_dq) {
+        // the first LSRK stage (A = 0) does not read dq at all
+        const bool use_dq = P.A != 0.0;
+        double dv[NQ][5];
+        if (use_dq) {
 #pragma unroll
             for (int t = 0; t < NQ; ++t)
 #pragma unroll

@@ -307,13 +307,12 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
     const int tid = threadIdx.x;
     const int el = tid / NQ2;
     const int m = tid - el * NQ2;
-    const int64_t e = (int64_t)lb * EPW + el;
-    const bool act = (el < EPW) && (e < P.ne);
+    const int64_t it = (int64_t)lb * EPW + el;  // traversal position
+    const bool act = (el < EPW) && (it < P.ne);
 
     int ec[3] = {0, 0, 0};
-    if (act) {
-        elem_coords(P, e, ec);
-    }
+    int64_t e = 0;
+    if (act) e = tile_element(P, it, ec);
     double phi_k[NQ];
     {
         const double dz = P.zhi - P.zlo;

@@ -19,8 +19,10 @@ three directions, Nq^3 nodes).  Face nodes per node: 6/Nq.
 
 Algorithmic HBM bytes per node and stage (FP64): read q and dq, write q_out
 and dq (4 x 40 B) plus the neighbours' face traces (6 faces of Nq^2 nodes of
-40 B per element: 240/Nq B per node).  One RHS evaluation without the update
-moves 40 + 40 + 240/Nq B per node.
+40 B per element: 240/Nq B per node).  The first of the five LSRK(5,4)
+stages has A_1 = 0 and reads no dq, so a stage launch moves on average
+(4 - 1/5) x 40 + 240/Nq B per node (200 B at N = 4).  One RHS evaluation
+without the update moves 40 + 40 + 240/Nq B per node.
 """
 from __future__ import annotations
 
@@ -47,7 +49,7 @@ def flops_per_node(N: int, stage: bool = True) -> float:
 
 def bytes_per_node(N: int, stage: bool = True, word: int = 8) -> float:
     Nq = N + 1
-    own = (4 if stage else 2) * 5 * word
+    own = (4.0 - 0.2 if stage else 2.0) * 5 * word
     return own + 6.0 * 5 * word / Nq
 
 

@@ -59,5 +59,28 @@ def test_invalid_arguments_fail_without_touching_the_device():
     d.grav = 9.81
     assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
     assert "periodic z" in esdg.last_error()
+    d.periodic[:] = [0, 0, 0]
+    d.K[:] = [4, 0, 4]  # empty mesh
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    assert "K[1]=0" in esdg.last_error()
+    d.K[:] = [2048, 2048, 1024]  # 2^32 elements
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    assert "2^31" in esdg.last_error()
+    d.K[:] = [2, 2, 2]
+    d.hi[:] = [1.0, 0.0, 1.0]
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    d.hi[:] = [1.0, 1.0, 1.0]
+    d.gamma = 1.0
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    d.gamma = 1.4
+    d.surface_flux = 7
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    d.surface_flux = 0
+    d.precision = 3
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    d.precision = 0
+    d.epw = 6  # not a compiled variant at N=4
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    assert "no kernel variant" in esdg.last_error()
     assert esdg.lib.esdg_rhs(None, None, None, 0.0) == esdg.ESDG_EINVAL
     assert esdg.lib.esdg_lgl_tables(9, None, None, None) == esdg.ESDG_EINVAL

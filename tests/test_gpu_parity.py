@@ -52,6 +52,9 @@ CASES = [
     ("N8", W.MeshSpec(8, (1, 1, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (0, 0, 0)), "iso_pert"),
     ("N4_single_elem_periodic", W.MeshSpec(4, (1, 1, 1), (0, 0, 0), (500.0, 500.0, 500.0), (1, 1, 0)), "iso_pert"),
     ("N4_ec_faces", W.MeshSpec(4, (2, 2, 3), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 1, 0), surface_flux=1), "iso_pert"),
+    # meshes larger than one traversal brick, with partial bricks in x, y and z
+    ("N2_partial_bricks", W.MeshSpec(2, (37, 7, 6), (0, 0, 0), (9000.0, 7000.0, 1100.0), (1, 0, 0)), "iso_pert"),
+    ("N5_partial_bricks", W.MeshSpec(5, (11, 5, 6), (0, 0, 0), (9000.0, 7000.0, 1100.0), (0, 1, 0), coriolis_f=1e-4), "iso_pert"),
     ("N4_no_gravity_periodic", W.MeshSpec(4, (2, 3, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 1, 1), grav=0.0), "iso_pert"),
     ("bubble_small", W.rising_bubble(K=(4, 4, 4)).mesh, "bubble"),
     ("channel_small", W.channel(K=(8, 4, 3)).mesh, "channel"),
@@ -124,6 +127,31 @@ def test_lsrk_100_steps_parity_and_graph():
     m.lsrk_run(q3, dq3, dt, 3)
     q3o = om.run(q0, dt, 3)
     assert np.all(err_net(q3.cpu().numpy(), q3o) <= TOL_STATE)
+
+
+STEP_CASES = [c for c in CASES if c[0] in ("N1_walls", "N3_ragged", "N4_ragged", "N5", "N7")]
+
+
+@pytest.mark.parametrize("name,spec,kind", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_lsrk_steps_parity_ragged_orders_and_stale_dq(name, spec, kind):
+    """Five LSRK steps on meshes whose element count leaves the last
+    workgroup partly empty, at orders with and without the early dq fetch;
+    dq starts as NaN, which the first stage (A = 0) must not read."""
+    esdg = _esdg()
+    om = _oracle_mesh(spec)
+    q0 = W.make_state(kind, om.coords(), spec, seed=5)
+    dt = om.cfl_dt(q0, 0.5)
+    q_or = om.run(q0, dt, 5)
+    m = esdg.Mesh(spec)
+    print(f"[{name}] ne={m.n_elem} epw={m.epw}", flush=True)
+    qg = torch.from_numpy(q0).cuda()
+    dq = torch.full_like(qg, float("nan"))
+    for _ in range(5):
+        m.lsrk_step(qg, dq, dt)
+    e = err_net(qg.cpu().numpy(), q_or)
+    print(f"[{name}] 5-step state rel L2 per var {np.array2string(e, precision=2)}", flush=True)
+    assert np.all(e <= TOL_STATE), e
+    assert torch.isfinite(dq).all()
 
 
 def test_entropy_and_conservation_diagnostics():
