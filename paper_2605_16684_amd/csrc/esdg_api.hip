@@ -278,7 +278,7 @@ int default_epw(int N)
     case 3: return 4;
     case 4: return 5;
     case 5: return 3;
-    case 6: return 2;
+    case 6: return 1;
     case 7: return 1;
     default: return 1;
     }

@@ -525,6 +525,27 @@ __device__ __forceinline__ void line_terms(const StageParams &P, const OrderTabl
     }
 }
 
+// Streams that the launch does not read again are written (and, for the
+// stage's dq, read) non-temporally, so that they do not evict the element
+// states the three phases re-read from L2: the RHS output at every order
+// (7-8 per cent faster); the stage's dq reads and q_out / dq writes from
+// N = 6 on (6-10 per cent faster there, 3-6 per cent slower at N = 4, 5).
+constexpr int NT_STAGE_MIN_NQ = 7;
+
+template <bool NT>
+__device__ __forceinline__ void store_f64(double *p, double v)
+{
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <bool NT>
+__device__ __forceinline__ double load_f64(const double *p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
 template <int NQ, int EPW>
 constexpr int block_threads()
 {
@@ -637,11 +658,12 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
                 Rv[2] -= P.cor_f * qv[t][1];
             }
 #pragma unroll
-            for (int v = 0; v < 5; ++v) rout[base0 + v * NQ3 + NQ2 * t] = Rv[v];
+            for (int v = 0; v < 5; ++v) store_f64<true>(&rout[base0 + v * NQ3 + NQ2 * t], Rv[v]);
         }
     } else {
         double *__restrict__ dqp = P.dq;
         double *__restrict__ qout = P.q_out;
+        constexpr bool nts = NQ >= NT_STAGE_MIN_NQ;
         // the first LSRK stage (A = 0) does not read dq at all
         const bool use_dq = P.A != 0.0;
         double dv[NQ][5];
@@ -649,7 +671,7 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
 #pragma unroll
             for (int t = 0; t < NQ; ++t)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) dv[t][v] = dqp[base0 + v * NQ3 + NQ2 * t];
+                for (int v = 0; v < 5; ++v) dv[t][v] = load_f64<nts>(&dqp[base0 + v * NQ3 + NQ2 * t]);
         }
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
@@ -664,8 +686,8 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 const double d = use_dq ? P.A * dv[t][v] + P.dt * Rv[v] : P.dt * Rv[v];
-                dqp[base0 + v * NQ3 + NQ2 * t] = d;
-                qout[base0 + v * NQ3 + NQ2 * t] = qv[t][v] + P.B * d;
+                store_f64<nts>(&dqp[base0 + v * NQ3 + NQ2 * t], d);
+                store_f64<nts>(&qout[base0 + v * NQ3 + NQ2 * t], qv[t][v] + P.B * d);
             }
         }
     }
