@@ -185,6 +185,38 @@ def serving_block(torch, throughput, n=96, steps=50, budget_gb=24.0, load=1.2, s
     return out
 
 
+def sweep_block(esdg, W, torch, orders=(3, 4, 5, 7), sizes=(2, 4, 8, 12, 16, 24, 32, 40),
+                max_nodes=4.0e7, steps=6):
+    """Throughput against mesh size per order: LSRK steps on rising-bubble
+    cubes of k^3 elements (small meshes leave the 256 CUs partly idle)."""
+    out = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for N in orders:
+        for k in sizes:
+            if k ** 3 * (N + 1) ** 3 > max_nodes:
+                break
+            wl = W.rising_bubble(N=N, K=(k, k, k))
+            m = esdg.Mesh(wl.mesh)
+            q = W.make_state(wl.kind, m.coords(), wl.mesh, seed=1).contiguous()
+            dq = torch.zeros_like(q)
+            dt = m.cfl_dt(q, wl.cfl)
+            m.lsrk_run(q, dq, dt, 2)
+            torch.cuda.synchronize()
+            e0.record()
+            m.lsrk_run(q, dq, dt, steps)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / steps
+            out.append({"N": N, "K": k, "elements": k ** 3, "nodes": m.n_nodes, "epw": m.epw,
+                        "step_ms": t * 1e3, "dof_rhs_per_s": m.n_nodes * 5 / t})
+            log(f"[bench] sweep N={N} K={k}^3: {m.n_nodes * 5 / t:.3e} DOF*RHS/s")
+            m.close()
+            del q, dq
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +231,8 @@ def main():
     ap.add_argument("--precision-workload", default="c3")
     ap.add_argument("--no-serving", action="store_true", help="skip the ensemble serving run")
     ap.add_argument("--serving-requests", type=int, default=96)
+    ap.add_argument("--sweep", action="store_true",
+                    help="also measure throughput against mesh size for N in 3, 4, 5, 7")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -323,6 +357,9 @@ def main():
         log("[bench] FP64 vs FP32-mixed ...")
         out["precision"] = precision_block(esdg, W, torch, workload=args.precision_workload)
         torch.cuda.empty_cache()
+    if args.sweep:
+        log("[bench] size sweep ...")
+        out["sweep"] = sweep_block(esdg, W, torch)
     if not args.no_serving:
         log("[bench] ensemble serving ...")
         out["serving"] = serving_block(torch, value, n=args.serving_requests)
