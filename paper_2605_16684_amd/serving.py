@@ -11,9 +11,10 @@ server
   launch per stage over all its members (``esdg.Pack``: a device descriptor
   table, one step = 5 packed stage kernels + a parity flip captured in a
   HIP graph) on its own stream, so buckets overlap on the device;
-* advances every active member by one step per scheduling round, admits new
-  arrivals between rounds as memory frees, and retires members that reach
-  their step count;
+* advances each bucket on its own: as soon as a bucket's step completes, its
+  members' latencies are recorded, finished members retire (freeing memory
+  for the queue), new members join, and the bucket's next step is launched
+  -- a bucket of small members is not held back by a bucket of large ones;
 * picks elements per workgroup per (N, precision) from an autotuner that
   times the compiled variants and caches the choice in JSON;
 * reports per-member step latency (completion of step s minus completion of
@@ -267,12 +268,14 @@ class GpuExecutor:
             mb.handle["parity"] ^= 1
         return ev
 
-    def wait(self, tokens: Dict[tuple, object]) -> Dict[tuple, float]:
-        out = {}
-        for key, ev in tokens.items():
-            ev.synchronize()
-            out[key] = self._dev_time(ev)
-        return out
+    def poll(self, tokens: Dict[tuple, object], until: Optional[float] = None) -> Dict[tuple, float]:
+        """Device completion times of the in-flight steps that have finished;
+        waits until at least one has, or until host time `until`."""
+        while True:
+            out = {key: self._dev_time(ev) for key, ev in tokens.items() if ev.query()}
+            if out or (until is not None and self.now() >= until):
+                return out
+            time.sleep(5e-5)
 
     def release(self, mb: Member):
         h = mb.handle
@@ -285,28 +288,49 @@ class GpuExecutor:
 
 
 class FakeExecutor:
-    """Simulated device: a step of a bucket takes overhead + sum over its
-    members of nodes x cost(N, precision); buckets launched in one round run
-    back to back.  Time is virtual."""
+    """Simulated device: a step of a bucket needs overhead + sum over its
+    members of nodes x cost(N, precision) of device time; the steps in flight
+    share the device equally (processor sharing, as concurrent streams share
+    the CUs).  Time is virtual."""
 
     def __init__(self, cost_per_node=None, overhead=20e-6, admit_cost=1e-3, fail_on=None):
         self.cost = cost_per_node or (lambda N, prec: 5 * 1e-10 * (1.0 if prec == FP64 else 0.8))
         self.overhead = overhead
         self.admit_cost = admit_cost
         self.clock = 0.0
+        self.running: Dict[tuple, float] = {}   # bucket -> remaining device time
+        self.finished: Dict[tuple, float] = {}  # bucket -> completion time
         self.buckets: Dict[tuple, List[Member]] = {}
         self.fail_on = fail_on or set()
 
     def now(self) -> float:
         return self.clock
 
-    def advance_to(self, t):
+    def _run_until(self, t):
+        while self.running and self.clock < t:
+            n = len(self.running)
+            step = min(self.running.values()) * n
+            if self.clock + step > t:
+                for k in self.running:
+                    self.running[k] -= (t - self.clock) / n
+                self.clock = t
+                return
+            self.clock += step
+            least = min(self.running.values())
+            for k in list(self.running):
+                self.running[k] -= least
+                if self.running[k] <= 1e-15:
+                    del self.running[k]
+                    self.finished[k] = self.clock
         self.clock = max(self.clock, t)
+
+    def advance_to(self, t):
+        self._run_until(t)
 
     def admit(self, req: Request):
         if req.rid in self.fail_on:
             raise RuntimeError(f"simulated failure admitting request {req.rid}")
-        self.clock += self.admit_cost
+        self._run_until(self.clock + self.admit_cost)
         return {"parity": 0}, self.clock
 
     def set_bucket(self, key, members):
@@ -317,14 +341,22 @@ class FakeExecutor:
 
     def launch_step(self, key):
         ms = self.buckets[key]
-        return self.overhead + sum(mb.req.nodes * self.cost(*key) for mb in ms)
+        self.running[key] = self.overhead + sum(mb.req.nodes * self.cost(*key) for mb in ms)
+        return key
 
-    def wait(self, tokens):
-        out = {}
-        for key, dur in tokens.items():
-            self.clock += dur
-            out[key] = self.clock
-        return out
+    def poll(self, tokens, until=None):
+        while True:
+            done = {k: self.finished.pop(k) for k in list(tokens) if k in self.finished}
+            if done:
+                return done
+            if not self.running:
+                return {}
+            n = len(self.running)
+            t_next = self.clock + min(self.running.values()) * n
+            if until is not None and until < t_next:
+                self._run_until(until)
+                return {k: self.finished.pop(k) for k in list(tokens) if k in self.finished}
+            self._run_until(t_next)
 
     def release(self, mb):
         return None
@@ -348,7 +380,7 @@ class RunStats:
     e2e_latency_mean_s: float
     peak_footprint_bytes: int
     hbm_budget_bytes: int
-    rounds: int
+    bucket_steps: int
     max_concurrent_members: int
     buckets_seen: int
 
@@ -374,10 +406,12 @@ class Server:
         used = peak = 0
         rejected = 0
         done: List[Member] = []
-        rounds = max_conc = 0
+        steps_launched = max_conc = 0
         buckets_seen = set()
+        inflight: Dict[tuple, object] = {}      # bucket -> completion token of its step
+        stepping: Dict[tuple, List[Member]] = {}  # bucket -> members of that step
         t_start = ex.now()
-        while pending or queue or any(active.values()):
+        while pending or queue or any(active.values()) or inflight:
             now = ex.now() - t_start
             while pending and pending[0].arrival <= now:
                 r = pending.pop(0)
@@ -404,7 +438,24 @@ class Server:
                 self.members[r.rid] = mb
                 dirty.add(r.key)
             n_act = sum(len(v) for v in active.values())
-            if n_act == 0:
+            max_conc = max(max_conc, n_act)
+            # idle buckets take their membership changes and launch a step
+            for key in list(dirty):
+                if key in inflight:
+                    continue
+                if active.get(key):
+                    ex.set_bucket(key, active[key])
+                    buckets_seen.add(key)
+                else:
+                    ex.drop_bucket(key)
+                    active.pop(key, None)
+                dirty.discard(key)
+            for key, ms in active.items():
+                if ms and key not in inflight:
+                    inflight[key] = ex.launch_step(key)
+                    stepping[key] = list(ms)  # members admitted later join after this step
+                    steps_launched += 1
+            if not inflight:
                 if not pending and not queue:
                     break
                 if pending:
@@ -417,20 +468,10 @@ class Server:
                         else:
                             time.sleep(min(wait, 0.05))
                 continue
-            max_conc = max(max_conc, n_act)
-            for key in list(dirty):
-                if active.get(key):
-                    ex.set_bucket(key, active[key])
-                    buckets_seen.add(key)
-                else:
-                    ex.drop_bucket(key)
-                    active.pop(key, None)
-            dirty.clear()
-            tokens = {key: ex.launch_step(key) for key, ms in active.items() if ms}
-            times = ex.wait(tokens)
-            rounds += 1
-            for key, t_end in times.items():
-                for mb in list(active[key]):
+            until = t_start + pending[0].arrival if pending else None
+            for key, t_end in ex.poll(inflight, until).items():
+                del inflight[key]
+                for mb in stepping.pop(key):
                     mb.latencies.append(t_end - mb.last_done)
                     mb.last_done = t_end
                     mb.steps_done += 1
@@ -458,5 +499,5 @@ class Server:
             queue_wait_p50_ms=float(np.percentile(waits, 50) * 1e3),
             queue_wait_p99_ms=float(np.percentile(waits, 99) * 1e3),
             e2e_latency_mean_s=float(e2e.mean()), peak_footprint_bytes=int(peak),
-            hbm_budget_bytes=self.budget, rounds=rounds, max_concurrent_members=max_conc,
+            hbm_budget_bytes=self.budget, bucket_steps=steps_launched, max_concurrent_members=max_conc,
             buckets_seen=len(buckets_seen))

@@ -46,7 +46,7 @@ def test_admission_binds_and_members_overlap():
     assert st.n_completed == 20
     assert 1 < st.max_concurrent_members < 20         # batched, but not all at once
     assert st.queue_wait_p99_ms > 0
-    # several (N, precision) buckets ran in the same rounds
+    # several (N, precision) buckets ran side by side
     assert st.buckets_seen >= 2
 
 
@@ -94,6 +94,25 @@ def test_statistics_are_computed_from_member_steps():
     srv1.run([one], realtime=False)
     lats = srv1.members[0].latencies
     assert lats[1] == pytest.approx(ex.overhead + one.nodes * ex.cost(4, S.FP64))
+
+
+def test_buckets_advance_independently():
+    # a bucket of one small member steps at its own pace next to a bucket of
+    # a large member: its step latency is set by its own work (the device is
+    # shared), not by the large member's step
+    big = S.Request(0, "channel", (12, 12, 12), 7, S.FP64, 0, 4, 0.0)
+    small = S.Request(1, "bubble", (2, 2, 2), 3, S.FP64, 1, 20, 0.0)
+    ex = S.FakeExecutor()
+    srv = S.Server(10 * (S.footprint_bytes(big) + S.footprint_bytes(small)), executor=ex)
+    st = srv.run([big, small], realtime=False)
+    assert st.n_completed == 2
+    t_big = ex.overhead + big.nodes * ex.cost(7, S.FP64)
+    t_small = ex.overhead + small.nodes * ex.cost(3, S.FP64)
+    lat_small = srv.members[1].latencies[1:]
+    assert max(lat_small) <= 2 * t_small + 1e-12       # shares the device with one other step
+    assert max(lat_small) < 0.1 * t_big
+    assert srv.members[1].finished < srv.members[0].finished
+    assert st.bucket_steps == big.steps + small.steps
 
 
 def test_footprint_formula():
