@@ -8,7 +8,13 @@
       HBM bytes per launch of each stage kernel from `--pmc FETCH_SIZE` and
       `--pmc WRITE_SIZE` runs, each scaled by what the same counter reads for
       the library's copy kernel of known size (1 GiB read + 1 GiB written,
-      run by `bench.py --calib-copy`).
+      run by `bench.py --calib-copy`);
+  python -m paper_2605_16684_amd.rocprof_report flops PMC_DB TRACE_DB
+          --workload NAME --cmd-pmc "..." --cmd-trace "..." [--out FILE]
+      executed FP64 work of each stage kernel from a `--pmc` run of the
+      SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 and SQ_INSTS_VALU_FLOPS_FP64
+      counters, divided by the kernel's average duration in a kernel trace,
+      against the MI355X FP64 vector peak.
 """
 from __future__ import annotations
 
@@ -111,6 +117,51 @@ def cmd_traffic(a):
             json.dump(data, f, indent=1, sort_keys=True)
 
 
+F64_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU_FLOPS_FP64",
+                "SQ_INSTS_VALU_FLOPS_FP64_TRANS", "SQ_INSTS_VALU", "SQ_WAVES")
+
+
+def cmd_flops(a):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_2605_16684_amd import perfmodel
+    per = {c: counter_by_kernel(a.pmc_db, c) for c in F64_COUNTERS}
+    durations = {name: avg for name, calls, total, avg in kernel_stats(a.trace_db)}
+    lines = [f"# Executed FP64 work per launch: {a.workload}", "",
+             "Commands (counter pass, then kernel trace for the durations):", "", "```",
+             a.cmd_pmc, a.cmd_trace, "```", "",
+             "Executed FP64 FLOPs = 64 lanes x (ADD + MUL + TRANS + 2 FMA) wave instructions "
+             "(an upper bound: the last wave of a 125-lane workgroup has 61 active lanes); "
+             "the FLOPS_FP64 x 64 column is the hardware's FLOP counter (which counts per wave "
+             "instruction) times the lanes, as a cross-check. Peak: "
+             f"{perfmodel.FP64_VECTOR_TFLOPS} TF/s FP64 vector.", "",
+             "| kernel | launches | VALU instr./wave | FP64 add/mul/fma/trans (M wave-instr.) "
+             "| FLOPs (instr., G) | FLOPS_FP64 x 64 (G) | avg (us) | executed TF/s | of peak |",
+             "|---|---:|---:|---|---:|---:|---:|---:|---:|"]
+    for name in sorted(per["SQ_INSTS_VALU_FMA_F64"]):
+        if "stage_" not in name:
+            continue
+        avg = {c: (sum(v) / len(v) if v else float("nan"))
+               for c, v in ((c, per[c].get(name, [])) for c in F64_COUNTERS)}
+        n = len(per["SQ_INSTS_VALU_FMA_F64"][name])
+        fl = 64.0 * (avg["SQ_INSTS_VALU_ADD_F64"] + avg["SQ_INSTS_VALU_MUL_F64"]
+                     + avg["SQ_INSTS_VALU_TRANS_F64"] + 2.0 * avg["SQ_INSTS_VALU_FMA_F64"])
+        hw = 64.0 * (avg["SQ_INSTS_VALU_FLOPS_FP64"] + avg["SQ_INSTS_VALU_FLOPS_FP64_TRANS"])
+        dur = durations.get(name)
+        tf = fl / (dur * 1e-6) / 1e12 if dur else float("nan")
+        lines.append(
+            f"| `{name[:70]}` | {n} | {avg['SQ_INSTS_VALU'] / avg['SQ_WAVES']:.0f} | "
+            f"{avg['SQ_INSTS_VALU_ADD_F64'] / 1e6:.1f} / {avg['SQ_INSTS_VALU_MUL_F64'] / 1e6:.1f} / "
+            f"{avg['SQ_INSTS_VALU_FMA_F64'] / 1e6:.1f} / {avg['SQ_INSTS_VALU_TRANS_F64'] / 1e6:.2f} | "
+            f"{fl / 1e9:.2f} | {hw / 1e9:.2f} | {dur if dur else float('nan'):.1f} | {tf:.1f} | "
+            f"{tf / perfmodel.FP64_VECTOR_TFLOPS:.2f} |")
+    txt = "\n".join(lines) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
+    print(txt)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -130,6 +181,14 @@ def main(argv=None):
     t.add_argument("--out")
     t.add_argument("--json")
     t.set_defaults(fn=cmd_traffic)
+    f = sub.add_parser("flops")
+    f.add_argument("pmc_db")
+    f.add_argument("trace_db")
+    f.add_argument("--workload", required=True)
+    f.add_argument("--cmd-pmc", required=True)
+    f.add_argument("--cmd-trace", required=True)
+    f.add_argument("--out")
+    f.set_defaults(fn=cmd_flops)
     a = ap.parse_args(argv)
     a.fn(a)
 

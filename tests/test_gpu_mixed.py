@@ -77,6 +77,28 @@ def test_mixed_rhs_error(name, spec, kind):
         assert en[3] <= max(1e-5, 50 * 6e-8 * k[3] * 1e-3), en[3]
 
 
+def test_mixed_full_size_sampled_channel_N7():
+    """The precision comparison's own configuration (160 x 24 x 10 channel
+    at N = 7, 19.7 M nodes) in the launch configuration bench.py times:
+    sampled elements of the mixed RHS against the FP64 oracle."""
+    from paper_2605_16684_amd import esdg
+    wl = W.WORKLOADS["c3"]
+    spec = wl.mesh
+    om = _oracle_mesh(spec)
+    xyz = om.coords()
+    q = W.make_state(wl.kind, xyz, spec, seed=1)
+    m = _mixed_mesh(spec, xyz, wl.kind)
+    del xyz
+    r = m.rhs(torch.from_numpy(q).cuda()).cpu().numpy()
+    rng = np.random.default_rng(0)
+    el = np.unique(np.concatenate([rng.choice(om.ne, 32, replace=False), [0, om.ne - 1]]))
+    r_or, g = om.rhs_elems(q, el)
+    eg = err_gross(r[el], r_or, g)
+    print(f"[mixed c3-sampled] err/gross={np.array2string(eg, precision=2)} epw={m.epw}", flush=True)
+    assert np.all(eg <= TOL_RHS_MIXED), eg
+    m.close()
+
+
 def test_mixed_well_balanced_reference_state():
     spec = W.MeshSpec(4, (2, 2, 3), (0, 0, 0), (2000.0, 2000.0, 30000.0), (1, 1, 0))
     om = _oracle_mesh(spec)
