@@ -16,15 +16,16 @@
 // both partners' contributions in registers -- the flux-symmetry saving of
 // Sec. 4.1 without the cyclic pair schedule, the antipodal half weights or
 // any cross-lane exchange; the gravity term's partner value is obtained by
-// the scaling G_ba = -G_ab b_a / b_b (Sec. 4.1).  Per-node primitives,
-// reciprocal-free quantities and the per-node logarithms (Sec. 4.1, T2-T4)
-// are computed once per node and staged in LDS.  The three directions run
-// in one launch as three phases (x, y, z) separated by workgroup barriers:
-// the x phase stores its sums in an LDS accumulator, the y phase adds to it,
-// and the z phase -- whose lane owns the nodes (i, j, 0..N) -- finishes R and
-// writes it (or the stage update) with coalesced stores.  Face fluxes are
-// evaluated by the lane that owns the line ending on that face, reading the
-// neighbour's coincident node straight from the stage input.
+// the scaling G_ba = -G_ab b_a / b_b (Sec. 4.1).  Each phase computes its
+// line's primitives in registers (Sec. 4.1, T2-T3) and the per-node
+// logarithms (T4) only for lines that can reach the log branch.  The three
+// directions run in one launch as three phases (x, y, z) separated by
+// workgroup barriers: the x phase stores its sums in an LDS accumulator, the
+// y phase adds to it, and the z phase -- whose lane owns the nodes
+// (i, j, 0..N) and keeps their states in registers -- finishes R and writes
+// it (or the stage update) with coalesced stores.  Face fluxes are evaluated
+// first in each phase by the lane that owns the line ending on that face,
+// reading the neighbour's coincident node straight from the stage input.
 #pragma once
 
 #include <hip/hip_runtime.h>
