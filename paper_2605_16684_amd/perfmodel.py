@@ -28,6 +28,7 @@ from __future__ import annotations
 
 import hashlib
 import os
+import re
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
@@ -60,13 +61,22 @@ def ridge_fp64() -> float:
 _SRC_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the HIP sources: hardware counters taken for an older kernel
-    are not reported for the current one."""
+def _code_only(text: str) -> str:
+    """Source text without comments and whitespace (string literals in the
+    kernels hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return re.sub(r"\s+", "", text)
+
+
+def kernel_source_hash(src_dir: str = _SRC_DIR) -> str:
+    """Hash of the HIP sources' code (comments and whitespace ignored):
+    hardware counters taken for an older kernel are not reported for the
+    current one."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(_SRC_DIR)):
+    for name in sorted(os.listdir(src_dir)):
         if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(_SRC_DIR, name), "rb") as f:
+            with open(os.path.join(src_dir, name), encoding="utf-8") as f:
                 h.update(name.encode())
-                h.update(f.read())
+                h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
