@@ -211,10 +211,11 @@ __device__ __forceinline__ void load_ref(const MixedParams &M, int64_t e, int n,
     pr = M.ref_p[e * NQ3 + n];
 }
 
-template <int NQ, int R>
+template <int NQ, int R, bool KEEP = false>
 __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const OrderTables &tb,
                                                  int m, int64_t e, const int ec[3],
-                                                 const double phi_k[NQ], float acc[NQ][5])
+                                                 const double phi_k[NQ], float acc[NQ][5],
+                                                 double (*qkeep)[5] = nullptr)
 {
     constexpr int NQ3 = NQ * NQ * NQ;
     const StageParams &P = M.s;
@@ -242,11 +243,31 @@ __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const Ord
         for (int side = 0; side < 2; ++side)
             plus_state<NQ, R>(P, m, ec, side, qc[side ? NQ - 1 : 0], qp[side]);
     }
+    if (KEEP) {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qkeep[t][v] = qc[t].v[v];
+    }
     NodeF nd[NQ];
 #pragma unroll
     for (int t = 0; t < NQ; ++t)
         nd[t] = primitives_mixed(qc[t], R == 2 ? phi_k[t] : phi_k[0], gm1, rrf[t], prf[t],
                                  zscale);
+
+    // face terms first: the conservative states die before the pair loop
+    if (faces) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int t = side ? NQ - 1 : 0;
+            float Fn[5];
+            face_flux_mixed<R>(nd[t], qc[t], qp[side], R == 2 ? phi_k[t] : phi_k[0],
+                               side ? 1.0 : -1.0, P, rrf[t], prf[t], Fn);
+            const float wi = tb.winvf[t];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[t][v] -= wi * Fn[v];
+        }
+    }
 
     if (P.mask & TERM_VOL) {
 #pragma unroll
@@ -282,18 +303,6 @@ __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const Ord
         }
     }
 
-    if (faces) {
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int t = side ? NQ - 1 : 0;
-            float Fn[5];
-            face_flux_mixed<R>(nd[t], qc[t], qp[side], R == 2 ? phi_k[t] : phi_k[0],
-                               side ? 1.0 : -1.0, P, rrf[t], prf[t], Fn);
-            const float wi = tb.winvf[t];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) acc[t][v] -= wi * Fn[v];
-        }
-    }
 }
 
 template <int NQ, int EPW, int MODE>
@@ -366,25 +375,27 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
     __syncthreads();
 
     if (!act) return;
+    const int64_t base0 = e * 5 * NQ3 + m;
+    const double *__restrict__ qin = P.q_in;
+    // the z line's states stay in registers for the update
+    double qv[NQ][5];
     if (vol_or_face) {
-        line_terms_mixed<NQ, 2>(M, tb, m, e, ec, phi_k, acc);
+        line_terms_mixed<NQ, 2, true>(M, tb, m, e, ec, phi_k, acc, qv);
     } else {
 #pragma unroll
         for (int t = 0; t < NQ; ++t)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) acc[t][v] = 0.0f;
+            for (int v = 0; v < 5; ++v) {
+                acc[t][v] = 0.0f;
+                qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
+            }
     }
     const bool src = (P.mask & TERM_SRC) != 0;
     // the reference part R(q_r) belongs to the pressure-gravity terms
     const bool with_ref = (P.mask & (TERM_VOL | TERM_FACE)) == (TERM_VOL | TERM_FACE);
-    const int64_t base0 = e * 5 * NQ3 + m;
-    const double *__restrict__ qin = P.q_in;
-    double qv[NQ][5];
     float rrm[NQ][3];
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             rrm[t][c] = with_ref ? M.rr_mom[(e * 3 + c) * NQ3 + m + NQ2 * t] : 0.0f;
@@ -405,11 +416,12 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
                 Rv[2] -= P.cor_f * qv[t][1];
             }
 #pragma unroll
-            for (int v = 0; v < 5; ++v) rout[base0 + v * NQ3 + NQ2 * t] = Rv[v];
+            for (int v = 0; v < 5; ++v) store_f64<true>(&rout[base0 + v * NQ3 + NQ2 * t], Rv[v]);
         }
     } else {
         double *__restrict__ dqp = P.dq;
         double *__restrict__ qout = P.q_out;
+        constexpr bool nts = NQ >= NT_STAGE_MIN_NQ;
         // the first LSRK stage (A = 0) does not read dq
         const bool use_dq = P.A != 0.0;
         double dv[NQ][5];
@@ -417,7 +429,7 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
 #pragma unroll
             for (int t = 0; t < NQ; ++t)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) dv[t][v] = dqp[base0 + v * NQ3 + NQ2 * t];
+                for (int v = 0; v < 5; ++v) dv[t][v] = load_f64<nts>(&dqp[base0 + v * NQ3 + NQ2 * t]);
         }
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
@@ -434,8 +446,8 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 const double d = use_dq ? P.A * dv[t][v] + P.dt * Rv[v] : P.dt * Rv[v];
-                dqp[base0 + v * NQ3 + NQ2 * t] = d;
-                qout[base0 + v * NQ3 + NQ2 * t] = qv[t][v] + P.B * d;
+                store_f64<nts>(&dqp[base0 + v * NQ3 + NQ2 * t], d);
+                store_f64<nts>(&qout[base0 + v * NQ3 + NQ2 * t], qv[t][v] + P.B * d);
             }
         }
     }
