@@ -388,12 +388,64 @@ class RunStats:
         return dataclasses.asdict(self)
 
 
+class RequestHandle:
+    """What `Server.submit` returns: the request's final state (host array,
+    when the executor keeps results) and its own latency figures once a
+    `Server.run_until_idle` call has served it."""
+
+    def __init__(self, server: "Server", req: Request):
+        self._server = server
+        self.req = req
+
+    def done(self) -> bool:
+        mb = self._server.members.get(self.req.rid)
+        return mb is not None and mb.steps_done >= self.req.steps
+
+    def result(self):
+        if not self.done():
+            raise RuntimeError(f"request {self.req.rid} has not completed "
+                               "(call Server.run_until_idle)")
+        return self._server.results.get(self.req.rid)
+
+    def stats(self) -> dict:
+        if not self.done():
+            raise RuntimeError(f"request {self.req.rid} has not completed")
+        mb = self._server.members[self.req.rid]
+        lat = np.array(mb.latencies)
+        return {"steps": mb.steps_done, "queue_wait_s": mb.admitted - self.req.arrival,
+                "e2e_latency_s": mb.finished - self.req.arrival,
+                "step_latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "step_latency_p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+
 class Server:
+    """Continuous-batching ensemble server.  Either hand `run` a whole
+    request stream with arrival times, or `submit` requests one by one and
+    call `run_until_idle`; `stats` returns the figures of the last run."""
+
     def __init__(self, hbm_budget_bytes: int, executor=None, autotuner: Optional[Autotuner] = None):
         self.budget = int(hbm_budget_bytes)
         self.ex = executor if executor is not None else GpuExecutor(autotuner)
         self.results: Dict[int, object] = {}
         self.members: Dict[int, Member] = {}
+        self._submitted: List[Request] = []
+        self._last: Optional[RunStats] = None
+
+    def submit(self, req: Request) -> RequestHandle:
+        """Queue a request (its `arrival` offset, in seconds after the start
+        of the next `run_until_idle`, is kept; 0 = at once)."""
+        if req.rid in self.members or any(r.rid == req.rid for r in self._submitted):
+            raise ValueError(f"request id {req.rid} already submitted")
+        self._submitted.append(req)
+        return RequestHandle(self, req)
+
+    def run_until_idle(self, realtime: bool = True) -> RunStats:
+        """Serve every submitted request to completion."""
+        reqs, self._submitted = self._submitted, []
+        return self.run(reqs, realtime=realtime)
+
+    def stats(self) -> dict:
+        return self._last.as_dict() if self._last is not None else {}
 
     def run(self, requests: List[Request], realtime: bool = True) -> RunStats:
         """Serve the stream until every request has completed (or was
@@ -491,7 +543,7 @@ class Server:
         waits = np.array([mb.admitted - mb.req.arrival for mb in done]) if done else np.zeros(1)
         e2e = np.array([mb.finished - mb.req.arrival for mb in done]) if done else np.zeros(1)
         work = sum(mb.req.nodes * 5 * mb.steps_done for mb in done)
-        return RunStats(
+        self._last = RunStats(
             n_requests=len(requests), n_completed=len(done), n_rejected=rejected,
             makespan_s=span, aggregate_dof_rhs_per_s=work / span,
             step_latency_p50_ms=float(np.percentile(lat, 50) * 1e3),
@@ -501,3 +553,4 @@ class Server:
             e2e_latency_mean_s=float(e2e.mean()), peak_footprint_bytes=int(peak),
             hbm_budget_bytes=self.budget, bucket_steps=steps_launched, max_concurrent_members=max_conc,
             buckets_seen=len(buckets_seen))
+        return self._last

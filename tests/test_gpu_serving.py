@@ -51,9 +51,9 @@ def test_alone_and_in_the_mix_give_identical_results(tmp_path):
     assert st.max_concurrent_members > 1
     for r in reqs:
         alone = S.Server(10 * S.footprint_bytes(r), executor=S.GpuExecutor(tuner, keep_results=True))
-        r1 = S.Request(r.rid, r.kind, r.K, r.N, r.precision, r.seed, r.steps, 0.0)
-        alone.run([r1])
-        a, b = srv.results[r.rid], alone.results[r.rid]
+        h = alone.submit(S.Request(r.rid, r.kind, r.K, r.N, r.precision, r.seed, r.steps, 0.0))
+        alone.run_until_idle()
+        a, b = srv.results[r.rid], h.result()
         assert a.shape == b.shape
         assert np.array_equal(a, b), (r, np.abs(a - b).max())
         assert np.all(np.isfinite(a))

@@ -115,6 +115,24 @@ def test_buckets_advance_independently():
     assert st.bucket_steps == big.steps + small.steps
 
 
+def test_submit_and_run_until_idle():
+    rs = _reqs(n=5, steps=3)
+    srv = S.Server(10 * max(S.footprint_bytes(r) for r in rs), executor=S.FakeExecutor())
+    handles = [srv.submit(r) for r in rs]
+    with pytest.raises(ValueError):
+        srv.submit(rs[0])
+    assert not any(h.done() for h in handles)
+    with pytest.raises(RuntimeError):
+        handles[0].result()
+    st = srv.run_until_idle(realtime=False)
+    assert st.n_completed == 5 and srv.stats()["n_completed"] == 5
+    for h in handles:
+        assert h.done()
+        hs = h.stats()
+        assert hs["steps"] == 3 and hs["e2e_latency_s"] >= hs["queue_wait_s"] >= 0
+        assert hs["step_latency_p99_ms"] >= hs["step_latency_p50_ms"] > 0
+
+
 def test_footprint_formula():
     r = S.Request(0, "bubble", (10, 10, 10), 4, S.FP64, 0, 1)
     assert S.footprint_bytes(r) >= 120 * r.nodes
