@@ -309,6 +309,21 @@ def main():
     torch.cuda.synchronize()
     t_rhs = e0.elapsed_time(e1) * 1e-3 / nr
 
+    # what this machine sustains in a plain device copy (context for the
+    # roofline fraction, which is against the published 8 TB/s)
+    nb = 1 << 27  # 1 GiB of doubles
+    a = torch.ones(nb, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(5):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 8 * nb * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+
     if args.calib_copy:
         n = 1 << 27  # 1 GiB of doubles
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -341,7 +356,9 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "algorithmic_flops_per_launch": flops_launch,
                      "fp64_tflops": achieved_tf,
-                     "fp64_frac": achieved_tf / perfmodel.FP64_VECTOR_TFLOPS},
+                     "fp64_frac": achieved_tf / perfmodel.FP64_VECTOR_TFLOPS,
+                     "device_copy_gbs": copy_gbs,
+                     "frac_of_device_copy": achieved_gbs / copy_gbs},
         "rhs_only": {"launch_ms": t_rhs * 1e3, "dof_rhs_per_s": nn / t_rhs,
                      "gbs": perfmodel.bytes_per_node(N, stage=False) * nn / t_rhs / 1e9,
                      "fp64_tflops": perfmodel.flops_per_node(N, stage=False) * nn / t_rhs / 1e12},
