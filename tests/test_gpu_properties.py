@@ -1,0 +1,160 @@
+"""Properties of the discretisation checked on the HIP path directly, besides
+its parity with the oracle: free-stream preservation, discrete well balancing
+of an isothermal atmosphere at rest (Sec. 3), discrete entropy conservation
+with entropy-conservative interface fluxes (Sec. 4), and FP32-mixed members
+of a packed launch evolving as on their own mesh.  The oracle is pinned to the
+same properties in tests/test_oracle_rhs.py; here it only supplies the gross
+term scale that each residual is measured against."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_16684_amd import workloads as W
+from tests._parity import err_gross
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _esdg():
+    from paper_2605_16684_amd import esdg
+    return esdg
+
+
+def _with_jumps(q, seed):
+    """Seeded node-by-node perturbation, so that states jump across every
+    face (a smooth field is continuous there and gives the interface
+    dissipation nothing to act on)."""
+    rng = np.random.default_rng(seed)
+    q = q.copy()
+    q *= (1.0 + 0.02 * rng.uniform(-1, 1, size=q[:, 0].shape))[:, None, :]
+    q[:, 1:4] += 5.0 * q[:, 0:1] * rng.uniform(-1, 1, size=q[:, 1:4].shape)
+    return q
+
+
+def _oracle_mesh(spec):
+    return O.Mesh(spec.N, spec.K, spec.lo, spec.hi, spec.periodic, gamma=spec.gamma,
+                  gas_R=spec.gas_R, grav=spec.grav, coriolis_f=spec.coriolis_f,
+                  surface_flux=spec.surface_flux)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 7, 8])
+def test_free_stream_is_preserved(N):
+    # uniform flow without gravity on a periodic box: R = 0 up to roundoff
+    esdg = _esdg()
+    spec = W.MeshSpec(N, (3, 2, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 1, 1), grav=0.0)
+    om = _oracle_mesh(spec)
+    q = W.constant_state(om.ne, om.Np)
+    _, g = om.rhs(q, gross=True)
+    m = esdg.Mesh(spec)
+    r = m.rhs(torch.from_numpy(q).cuda()).cpu().numpy()
+    eg = err_gross(r, 0 * r, g)
+    print(f"[free stream N={N}] |R|/gross = {np.array2string(eg, precision=2)}", flush=True)
+    assert np.all(eg <= 1e-14), eg
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 7])
+def test_isothermal_state_at_rest_is_balanced(N):
+    # gravity balances the discrete pressure gradient pair by pair, and the
+    # wall faces see zero normal velocity: R = 0 up to roundoff
+    esdg = _esdg()
+    spec = W.MeshSpec(N, (2, 2, 4), (0, 0, 0), (2000.0, 2000.0, 30000.0), (1, 1, 0))
+    om = _oracle_mesh(spec)
+    q = W.state_iso_rest(om.coords(), spec, T=250.0)
+    _, g = om.rhs(q, gross=True)
+    m = esdg.Mesh(spec)
+    r = m.rhs(torch.from_numpy(q).cuda()).cpu().numpy()
+    eg = err_gross(r, 0 * r, g)
+    print(f"[balanced N={N}] |R|/gross = {np.array2string(eg, precision=2)} "
+          f"max|R_rhow| = {np.abs(r[:, 3]).max():.2e}", flush=True)
+    assert np.all(eg <= 1e-14), eg
+    assert np.abs(r[:, 3]).max() < 1e-9
+
+
+def test_balanced_state_stays_at_rest_over_steps():
+    # 20 LSRK(5,4) steps of the state at rest leave it at rest
+    esdg = _esdg()
+    spec = W.MeshSpec(4, (2, 2, 4), (0, 0, 0), (2000.0, 2000.0, 30000.0), (1, 1, 0))
+    om = _oracle_mesh(spec)
+    q0 = W.state_iso_rest(om.coords(), spec)
+    m = esdg.Mesh(spec)
+    q = torch.from_numpy(q0).cuda()
+    dq = torch.zeros_like(q)
+    dt = m.cfl_dt(q, 0.5)
+    m.lsrk_run(q, dq, dt, 20)
+    q1 = q.cpu().numpy()
+    vel = np.abs(q1[:, 1:4] / q1[:, 0:1]).max()
+    rel = [np.abs(q1[:, v] - q0[:, v]).max() / np.abs(q0[:, v]).max() for v in (0, 4)]
+    print(f"[at rest, 20 steps] max|u| = {vel:.2e} rel change rho {rel[0]:.2e} E {rel[1]:.2e}",
+          flush=True)
+    # the oracle's own run of this case: |u| ~ 3e-13, relative change ~ 1e-15
+    assert vel < 1e-11
+    assert max(rel) <= 1e-13
+
+
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_entropy_conserved_with_ec_faces(N):
+    # periodic box without gravity and the entropy-conservative interface
+    # flux: the discrete production sum J w v . R vanishes
+    esdg = _esdg()
+    spec = W.MeshSpec(N, (2, 3, 2), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 1), grav=0.0,
+                      surface_flux=1)
+    om = _oracle_mesh(spec)
+    q = _with_jumps(W.state_iso_pert(om.coords(), spec, seed=3, amp_rho=5e-2, amp_u=20.0), 3)
+    _, g = om.rhs(q, gross=True)
+    phi = om.phi()
+    v = np.stack([O.entropy_vars(q[e, :, n], phi[e, n]) for e in range(om.ne)
+                  for n in range(om.Np)]).reshape(om.ne, om.Np, 5).transpose(0, 2, 1)
+    _, w, _, _ = om.tables()
+    wq = np.einsum("i,j,k->kji", w, w, w).reshape(-1) * (om.h[0] * om.h[1] * om.h[2] / 8.0)
+    scale = (wq[None, None, :] * np.abs(v) * g).sum()
+    m = esdg.Mesh(spec)
+    eg = m.entropy(torch.from_numpy(q).cuda())
+    print(f"[entropy EC N={N}] production {eg[3]:.3e} scale {scale:.3e}", flush=True)
+    assert abs(eg[3]) <= 1e-14 * scale
+
+
+def test_entropy_dissipated_with_rusanov_faces_and_conserved_with_ec():
+    # the same discontinuous state, faces switched: Rusanov production is
+    # negative and exceeds the EC residual by many orders of magnitude (the
+    # oracle: -1.1e6 against 2e-8)
+    esdg = _esdg()
+    base = dict(N=3, K=(3, 2, 2), lo=(0, 0, 0), hi=(1000.0, 1000.0, 1000.0), periodic=(1, 1, 1),
+                grav=0.0)
+    s_ec, s_ru = W.MeshSpec(**base, surface_flux=1), W.MeshSpec(**base, surface_flux=0)
+    om = _oracle_mesh(s_ec)
+    q = _with_jumps(W.state_iso_pert(om.coords(), s_ec, seed=8, amp_rho=5e-2, amp_u=20.0), 8)
+    q = torch.from_numpy(q).cuda()
+    e_ec = esdg.Mesh(s_ec).entropy(q)[3]
+    e_ru = esdg.Mesh(s_ru).entropy(q)[3]
+    print(f"[entropy] EC {e_ec:.3e} Rusanov {e_ru:.3e}", flush=True)
+    assert e_ru < 0.0
+    assert abs(e_ec) < 1e-10 * abs(e_ru)
+
+
+def test_packed_mixed_members_equal_single_mesh_steps():
+    # FP32-mixed members of one packed launch evolve bit for bit as they do
+    # stepped on their own mesh
+    esdg = _esdg()
+    from paper_2605_16684_amd import serving as S
+    reqs = [S.Request(0, "channel", (4, 3, 2), 4, S.FP32_MIXED, 1, 3),
+            S.Request(1, "bubble", (3, 2, 3), 4, S.FP32_MIXED, 2, 3)]
+    members, ref = [], []
+    for r in reqs:
+        m, q, _ = S._make_member_mesh(r)
+        assert m.precision == S.FP32_MIXED
+        dt = m.cfl_dt(q, 0.5)
+        members.append((m, q.clone(), torch.empty_like(q), torch.zeros_like(q), dt))
+        qa, dqa = q.clone(), torch.zeros_like(q)
+        for _ in range(3):
+            m.lsrk_step(qa, dqa, dt)
+        ref.append(qa)
+    pack = esdg.Pack()
+    pack.set_members([x[0] for x in members], [x[1] for x in members], [x[2] for x in members],
+                     [x[3] for x in members], [x[4] for x in members], [0, 0])
+    pack.step(3)
+    torch.cuda.synchronize()
+    for (m, q0, q1, dq, dt), qa in zip(members, ref):
+        assert torch.isfinite(q1).all()
+        assert torch.equal(q1, qa)
+    pack.close()
