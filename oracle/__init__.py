@@ -19,7 +19,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 TERM_VOL, TERM_FACE, TERM_SRC = 1, 2, 4
 TERM_ALL = TERM_VOL | TERM_FACE | TERM_SRC
-SURF_RUSANOV, SURF_EC = 0, 1
+SURF_RUSANOV, SURF_EC, SURF_MATRIX = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)

@@ -33,7 +33,9 @@
  *     (a+b) / (2 + u(2/3 + u(2/5 + u 2/7))), else (b-a)/(ln b - ln a);
  *   - face flux: entropy-conservative flux plus Rusanov (local Lax-Friedrichs)
  *     dissipation 0.5*lambda*(q+ - q-), lambda = max over both sides of
- *     |u.n| + c; ESDG_SURF_EC drops the dissipation;
+ *     |u.n| + c; ESDG_SURF_EC drops the dissipation; ESDG_SURF_MATRIX uses
+ *     the entropy-stable matrix dissipation of matrix_dissipation() (the
+ *     paper's choice, Sec. 3, whose formula it cites but does not print);
  *   - reflecting walls: mirror state (rho, m - 2 (m.n) n, E), phi+ = phi-;
  *   - Coriolis: f-plane, h = (0, f m_y, -f m_x, 0, 0);
  *   - time step: dt = CFL / ((N+1) max_a sum_r (|u_r| + c) / h_r).
@@ -49,6 +51,7 @@
 #define NQMAX 16
 #define SURF_RUSANOV 0
 #define SURF_EC 1
+#define SURF_MATRIX 2
 #define TERM_VOL 1
 #define TERM_FACE 2
 #define TERM_SRC 4
@@ -331,14 +334,117 @@ void oracle_two_point_flux(int r, const double qa[5], const double qb[5], double
            0.5 * (pa * ub[r] + pb * ua[r]);
 }
 
+/* Entropy-stable matrix dissipation D for a face normal along axis r (the
+ * Roe-type dissipation the paper adds to the entropy-conservative face flux,
+ * Sec. 3; the formula is cited there, not printed, and is read here as the
+ * standard construction).  With the averaged state
+ *   rho_hat = {{rho}}_log,  u_hat = {{u}},  p_hat = {{rho}} / (2 {{b}}),
+ *   |u|^2_bar = 2 |u_hat|^2 - {{|u|^2}},
+ *   h_hat = gamma / (2 (gamma - 1) {{b}}_log) + |u|^2_bar / 2,
+ *   a_hat = sqrt(gamma p_hat / rho_hat),
+ * R holds the right eigenvectors of the normal flux Jacobian (acoustic,
+ * entropy, two shear, acoustic), |lambda| the moduli of their eigenvalues
+ * u_n -+ a, u_n, u_n, u_n, and t the diagonal scaling for which
+ * R diag(t) R^T = dq/dv at equal states:
+ *   D = R diag(|lambda| t) R^T [[v]],   [[v]] = v(q+) - v(q-).
+ * D is symmetric positive semi-definite in [[v]], so it only removes
+ * entropy, and it does not depend on the sign of the normal.  Both sides of
+ * a face share phi and E contains rho*phi: D is formed for the state without
+ * the potential energy, (rho, m, E - rho phi), whose entropy variables lack
+ * the 2 b phi term, and the energy component then gains phi times the mass
+ * component (that map is linear with unit diagonal, so this is the same
+ * operator written for the total energy).
+ * Pins: the small-jump limit |A| [[q]], entropy stability, antisymmetry and
+ * an exactly kept stationary contact (which fixes the log-mean in h_hat).
+ * The averages chosen for p_hat, |u|^2_bar and a_hat enter only at second
+ * order in the jump: beyond that they are a reading, parity unpinned. */
+static void matrix_dissipation(int r, const double qm[5], const double qp[5], double phi,
+                               double gamma, double D[5])
+{
+    double gm1 = gamma - 1.0;
+    double rm = qm[0], rp = qp[0], um[3], up[3];
+    for (int c = 0; c < 3; ++c) {
+        um[c] = qm[1 + c] / rm;
+        up[c] = qp[1 + c] / rp;
+    }
+    double pm = pressure(qm, phi, gamma), pp = pressure(qp, phi, gamma);
+    double bm = rm / (2.0 * pm), bp = rp / (2.0 * pp);
+    double uum = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+    double uup = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+
+    /* averaged state */
+    double rho_hat = oracle_logmean(rm, rp);
+    double b_ln = oracle_logmean(bm, bp);
+    double uh[3];
+    for (int c = 0; c < 3; ++c) uh[c] = 0.5 * (um[c] + up[c]);
+    double p_hat = 0.5 * (rm + rp) / (2.0 * 0.5 * (bm + bp));
+    double u2bar = 2.0 * (uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2]) - 0.5 * (uum + uup);
+    double h_hat = gamma / (2.0 * gm1 * b_ln) + 0.5 * u2bar;
+    double a_hat = sqrt(gamma * p_hat / rho_hat);
+
+    /* jump of the entropy variables without the potential energy,
+     * v = ((gamma - s)/(gamma - 1) - b |u|^2, 2 b u, -2 b), s = ln p - gamma ln rho;
+     * a jump of logarithms is taken as the logarithm of the ratio */
+    double ds = log(pp / pm) - gamma * log(rp / rm);
+    double dv[5];
+    dv[0] = -ds / gm1 - (bp * uup - bm * uum);
+    for (int c = 0; c < 3; ++c) dv[1 + c] = 2.0 * (bp * up[c] - bm * um[c]);
+    dv[4] = -2.0 * (bp - bm);
+
+    /* eigenvectors (columns), normal e_r, tangents the other two axes */
+    int t1 = (r + 1) % 3, t2 = (r + 2) % 3;
+    double un = uh[r];
+    double Rm[5][5];
+    memset(Rm, 0, sizeof(Rm));
+    Rm[0][0] = 1.0;
+    Rm[0][1] = 1.0;
+    Rm[0][4] = 1.0;
+    for (int c = 0; c < 3; ++c) {
+        Rm[1 + c][0] = uh[c] - (c == r ? a_hat : 0.0);
+        Rm[1 + c][1] = uh[c];
+        Rm[1 + c][4] = uh[c] + (c == r ? a_hat : 0.0);
+    }
+    Rm[1 + t1][2] = 1.0;
+    Rm[1 + t2][3] = 1.0;
+    Rm[4][0] = h_hat - a_hat * un;
+    Rm[4][1] = 0.5 * u2bar;
+    Rm[4][2] = uh[t1];
+    Rm[4][3] = uh[t2];
+    Rm[4][4] = h_hat + a_hat * un;
+    double lam[5] = {fabs(un - a_hat), fabs(un), fabs(un), fabs(un), fabs(un + a_hat)};
+    double tsc[5] = {rho_hat / (2.0 * gamma), rho_hat * gm1 / gamma, p_hat, p_hat,
+                     rho_hat / (2.0 * gamma)};
+
+    double w[5];
+    for (int k = 0; k < 5; ++k) {
+        double acc = 0.0;
+        for (int v = 0; v < 5; ++v) acc += Rm[v][k] * dv[v];
+        w[k] = lam[k] * tsc[k] * acc;
+    }
+    for (int v = 0; v < 5; ++v) {
+        double acc = 0.0;
+        for (int k = 0; k < 5; ++k) acc += Rm[v][k] * w[k];
+        D[v] = acc;
+    }
+    D[4] += phi * D[0];
+}
+
 /* Normal face flux F* . n for the face with outward normal n = s e_r (s = +-1):
  * s f_r(q-, q+) - lambda/2 (q+ - q-) with lambda = max(|u.n| + c) (Rusanov),
- * or without dissipation for the entropy-conservative face flux. */
+ * s f_r(q-, q+) - D/2 with the matrix dissipation above, or without
+ * dissipation for the entropy-conservative face flux.  Faces have
+ * phi+ = phi-. */
 void oracle_surface_flux(int r, int s, const double qm[5], const double qp[5], double phim,
                          double phip, double gamma, int surf, double Fn[5])
 {
     double F[5];
     oracle_two_point_flux(r, qm, qp, phim, phip, gamma, F);
+    if (surf == SURF_MATRIX) {
+        double D[5];
+        matrix_dissipation(r, qm, qp, phim, gamma, D);
+        for (int v = 0; v < 5; ++v) Fn[v] = s * F[v] - 0.5 * D[v];
+        return;
+    }
     double lam = 0.0;
     if (surf == SURF_RUSANOV) {
         double pm = pressure(qm, phim, gamma), pp = pressure(qp, phip, gamma);

@@ -224,3 +224,107 @@ def test_surface_flux(r):
         # dissipation is entropy dissipative: [[v]] . (F_rus - F_ec) <= 0
         dv = _v_complex_step(qp, phi) - _v_complex_step(q, phi)
         assert dv @ (Fr - Fe) <= 1e-12 * np.abs(dv * (Fr - Fe)).sum()
+
+
+def _jacobian_complex_step(r, q, phi):
+    # d f_r / dq of the test's own physical flux, exact to roundoff
+    A = np.zeros((5, 5))
+    h = 1e-30
+    for k in range(5):
+        qc = q.astype(complex)
+        step = h * max(1.0, abs(q[k]))
+        qc[k] += 1j * step
+        A[:, k] = _physical_flux_c(r, qc, phi).imag / step
+    return A
+
+
+def _physical_flux_c(r, q, phi):
+    p = (G - 1) * (q[4] - 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0] - q[0] * phi)
+    u = q[1:4] / q[0]
+    f = np.zeros(5, dtype=complex)
+    f[0] = q[1 + r]
+    f[1:4] = q[1:4] * u[r]
+    f[1 + r] += p
+    f[4] = (q[4] + p) * u[r]
+    return f
+
+
+def _matrix_diss(r, s, qm, qp, phi):
+    """D of F* = s f_r(q-, q+) - D/2 for the matrix-dissipation face flux."""
+    Fm = O.surface_flux(r, s, qm, qp, phi, phi, G, O.SURF_MATRIX)
+    Fe = O.surface_flux(r, s, qm, qp, phi, phi, G, O.SURF_EC)
+    return -2.0 * (Fm - Fe)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_matrix_dissipation_vanishes_at_equal_states(r):
+    rng = np.random.default_rng(70 + r)
+    for _ in range(50):
+        phi = rng.uniform(0, 3e5)
+        q = _state(rng, phi)
+        for s in (-1, 1):
+            Fm = O.surface_flux(r, s, q, q, phi, phi, G, O.SURF_MATRIX)
+            assert np.array_equal(Fm, O.surface_flux(r, s, q, q, phi, phi, G, O.SURF_EC))
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_matrix_dissipation_small_jump_is_roe_matrix(r):
+    # For a small jump D -> |A| [[q]] with |A| = V |Lambda| V^-1 the modulus of
+    # the normal flux Jacobian (eigen-decomposition by numpy of the
+    # complex-step Jacobian of the physical flux, gravity included): pins the
+    # eigenvectors, eigenvalues, scaling and averages to first order.
+    rng = np.random.default_rng(80 + r)
+    for _ in range(30):
+        phi = rng.uniform(0, 3e5)
+        q = _state(rng, phi)
+        dq = _state(rng, phi) - q
+        eps = 1e-6
+        qp = q + eps * dq
+        qbar = 0.5 * (q + qp)
+        lam, V = np.linalg.eig(_jacobian_complex_step(r, qbar, phi))
+        absA = (V @ np.diag(np.abs(lam)) @ np.linalg.inv(V)).real
+        want = absA @ (qp - q)
+        for s in (-1, 1):
+            D = _matrix_diss(r, s, q, qp, phi)
+            scale = np.abs(absA) @ np.abs(qp - q)
+            assert np.all(np.abs(D - want) <= 1e-5 * scale), (D, want)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_matrix_dissipation_is_entropy_stable_and_antisymmetric(r):
+    rng = np.random.default_rng(90 + r)
+    for _ in range(200):
+        phi = rng.uniform(0, 3e5)
+        qm, qp = _state(rng, phi), _state(rng, phi)
+        dv = _v_complex_step(qp, phi) - _v_complex_step(qm, phi)
+        D = _matrix_diss(r, 1, qm, qp, phi)
+        # [[v]] . D >= 0: the face only removes entropy
+        assert dv @ D >= -1e-12 * np.abs(dv * D).sum()
+        assert dv @ D > 0.0
+        # independent of the normal's sign; the neighbour sees -F*
+        assert np.allclose(_matrix_diss(r, -1, qm, qp, phi), D, rtol=1e-12,
+                           atol=1e-12 * np.abs(D).max())
+        Fa = O.surface_flux(r, 1, qm, qp, phi, phi, G, O.SURF_MATRIX)
+        Fb = O.surface_flux(r, -1, qp, qm, phi, phi, G, O.SURF_MATRIX)
+        assert np.allclose(Fa, -Fb, rtol=1e-12, atol=1e-12 * np.abs(Fa).max())
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_matrix_dissipation_keeps_a_stationary_contact(r):
+    # rho jumps, p and the velocity are equal on both sides and u.n = 0: the
+    # Roe-type dissipation vanishes (Rusanov's does not); this fixes the
+    # log-mean enthalpy average h_hat, with which the acoustic projections
+    # reduce to [[ln p]] = 0
+    rng = np.random.default_rng(100 + r)
+    for _ in range(50):
+        phi = rng.uniform(0, 3e5)
+        p = rng.uniform(3e3, 1e5)
+        u = rng.uniform(-40, 40, 3)
+        u[r] = 0.0
+        ra, rb = rng.uniform(0.05, 1.5, 2)
+        mk = lambda rho: np.array([rho, *(rho * u), p / (G - 1) + 0.5 * rho * (u @ u) + rho * phi])
+        qm, qp = mk(ra), mk(rb)
+        D = _matrix_diss(r, 1, qm, qp, phi)
+        Dr = -2.0 * (O.surface_flux(r, 1, qm, qp, phi, phi, G, O.SURF_RUSANOV)
+                     - O.surface_flux(r, 1, qm, qp, phi, phi, G, O.SURF_EC))
+        assert np.all(np.abs(D) <= 1e-11 * np.abs(Dr).max()), (D, Dr)
