@@ -53,7 +53,7 @@ enum {
     ESDG_ENOTIMPL = -5
 };
 
-enum { ESDG_SURF_RUSANOV = 0, ESDG_SURF_EC = 1 };
+enum { ESDG_SURF_RUSANOV = 0, ESDG_SURF_EC = 1, ESDG_SURF_MATRIX = 2 };
 enum { ESDG_FP64 = 0, ESDG_FP32_MIXED = 1 };
 enum { ESDG_TERM_VOL = 1, ESDG_TERM_FACE = 2, ESDG_TERM_SRC = 4, ESDG_TERM_ALL = 7 };
 
@@ -68,7 +68,10 @@ typedef struct esdg_mesh *esdg_mesh_t;
  *   grav         gravitational acceleration in -z (9.81)
  *   coriolis_f   f-plane Coriolis parameter (0 or e.g. 1e-4 s^-1)
  *   surface_flux ESDG_SURF_RUSANOV (EC flux + local Lax-Friedrichs
- *                dissipation) or ESDG_SURF_EC (no dissipation)
+ *                dissipation), ESDG_SURF_EC (no dissipation) or
+ *                ESDG_SURF_MATRIX (EC flux + entropy-stable matrix
+ *                dissipation R |Lambda| T R^T [[v]], the Roe-type dissipation
+ *                of the paper's surface flux, Sec. 3)
  *   precision    ESDG_FP64 or ESDG_FP32_MIXED
  *   ref_rho/ref_p  FP32_MIXED only: device arrays [e][n] (FP64) holding the
  *                hydrostatic reference state; NULL for FP64

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 def hipcc_cmd(out, extra=()):
     return ["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
             "-shared", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
+            "-ffp-contract=fast-honor-pragmas", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
             *extra, "-o", out, SRC]
 
 

@@ -542,7 +542,8 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         return fail(ESDG_EINVAL, "periodic z with grav != 0 (phi = g z is not periodic)");
     if (!(d->gamma > 1.0) || !(d->gas_R > 0.0))
         return fail(ESDG_EINVAL, "gamma must be > 1 and gas_R > 0");
-    if (d->surface_flux != ESDG_SURF_RUSANOV && d->surface_flux != ESDG_SURF_EC)
+    if (d->surface_flux != ESDG_SURF_RUSANOV && d->surface_flux != ESDG_SURF_EC &&
+        d->surface_flux != ESDG_SURF_MATRIX)
         return fail(ESDG_EINVAL, "unknown surface flux %d", d->surface_flux);
     if (d->precision != ESDG_FP64 && d->precision != ESDG_FP32_MIXED)
         return fail(ESDG_EINVAL, "unknown precision %d", d->precision);

@@ -35,6 +35,9 @@ namespace esdg {
 
 constexpr int NQ_MAX = 9;  // polynomial order N <= 8
 
+// Interface dissipation (values of esdg_mesh_desc.surface_flux).
+constexpr int SURF_RUSANOV = 0, SURF_EC = 1, SURF_MATRIX = 2;
+
 // LGL tables of one order, filled once per device by the host.
 struct OrderTables {
     double xi[NQ_MAX];
@@ -277,10 +280,79 @@ __device__ __forceinline__ Node primitives(const Cons &c, double phi, double gm1
     return n;
 }
 
+// Entropy-stable matrix dissipation D = R |Lambda| T R^T [[v]] for a face
+// normal along axis R (the Roe-type dissipation of the paper's surface flux,
+// Sec. 3).  R: right eigenvectors of the normal flux Jacobian (acoustic,
+// entropy, two shear, acoustic) with eigenvalues u_n - a, u_n, u_n, u_n,
+// u_n + a, and T the scaling (rho/(2 gamma), rho (gamma-1)/gamma, p, p,
+// rho/(2 gamma)) for which R T R^T = dq/dv, all at the averaged state
+//   rho_hat = {{rho}}_log, u_hat = {{u}}, p_hat = {{rho}} / {{z}},
+//   |u|^2_bar = 2 |u_hat|^2 - {{|u|^2}},
+//   h_hat = gamma / ((gamma-1) {{z}}_log) + |u|^2_bar / 2,
+//   a_hat^2 = gamma p_hat / rho_hat      (z = rho/p = 2b).
+// It is formed for the state without potential energy, whose entropy
+// variables are ((gamma - s)/(gamma-1) - z|u|^2/2, z u, -z); both sides share
+// phi, so the energy component then gains phi times the mass component.  The
+// jumps of the logarithms come from the log-means of the EC flux:
+// [[ln rho]] = [[rho]] / {{rho}}_log and [[ln z]] = [[z]] / {{z}}_log.
+template <int R>
+__device__ __forceinline__ void matrix_dissipation(const Node &a, const Node &b, double rho_ln,
+                                                   double izln, double phi,
+                                                   const StageParams &P, double D[5])
+{
+    constexpr int T1 = (R + 1) % 3, T2 = (R + 2) % 3;
+    const double g = P.gamma, gm1i = P.gm1i;
+    const double u[3] = {a.h0 + b.h0, a.h1 + b.h1, a.h2 + b.h2};
+    const double ka = a.h0 * a.h0 + a.h1 * a.h1 + a.h2 * a.h2;  // |u_a|^2 / 4
+    const double kb = b.h0 * b.h0 + b.h1 * b.h1 + b.h2 * b.h2;
+    const double u2bar = 2.0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 2.0 * (ka + kb);
+    const double phat = fdiv(a.r + b.r, a.z + b.z);
+    const double hhat = g * gm1i * izln + 0.5 * u2bar;
+    const double ahat = sqrt_pos(g * fdiv(phat, rho_ln));
+
+    // Jumps of products are formed without FMA contraction: fma(x_b, y_b,
+    // -x_a y_a) leaves the rounding error of x_a y_a where the states are
+    // equal, and the dissipation must vanish there exactly.
+    const double dz = b.z - a.z;
+    double dv[5];
+    {
+#pragma clang fp contract(off)
+        const double zk_a = a.z * ka, zk_b = b.z * kb;
+        dv[0] = fdiv(b.r - a.r, rho_ln) + gm1i * (dz * izln) - 2.0 * (zk_b - zk_a);
+        dv[1] = 2.0 * (b.z * b.h0 - a.z * a.h0);
+        dv[2] = 2.0 * (b.z * b.h1 - a.z * a.h1);
+        dv[3] = 2.0 * (b.z * b.h2 - a.z * a.h2);
+    }
+    dv[4] = -dz;
+
+    const double un = u[R];
+    const double c0 = dv[0] + u[0] * dv[1] + u[1] * dv[2] + u[2] * dv[3] + hhat * dv[4];
+    const double an = ahat * (dv[1 + R] + un * dv[4]);
+    const double ta = rho_ln * (0.5 / g);
+    const double te = rho_ln * (g - 1.0) / g;
+    const double aun = fabs(un);
+    const double s0 = fabs(un - ahat) * ta * (c0 - an);
+    const double s4 = fabs(un + ahat) * ta * (c0 + an);
+    const double s1 = aun * te * (c0 - (hhat - 0.5 * u2bar) * dv[4]);
+    const double s2 = aun * phat * (dv[1 + T1] + u[T1] * dv[4]);
+    const double s3 = aun * phat * (dv[1 + T2] + u[T2] * dv[4]);
+    const double sa = s0 + s1 + s4, sd = s4 - s0;
+    D[0] = sa;
+    D[1] = u[0] * sa;
+    D[2] = u[1] * sa;
+    D[3] = u[2] * sa;
+    D[1 + R] += ahat * sd;
+    D[1 + T1] += s2;
+    D[1 + T2] += s3;
+    D[4] = hhat * (s0 + s4) + ahat * un * sd + 0.5 * u2bar * s1 + u[T1] * s2 + u[T2] * s3 +
+           phi * sa;
+}
+
 // Normal face flux F*.n for outward normal n = s e_R at a face node with
 // geopotential phi on both sides (the face nodes of neighbours coincide, so
-// the gravity term vanishes): s f_R(q-, q+) - lambda/2 (q+ - q-), with
-// lambda = max(|u_R| + c) over both sides (Rusanov), c^2 = gamma p/rho.
+// the gravity term vanishes): s f_R(q-, q+) minus the dissipation, either
+// lambda/2 (q+ - q-) with lambda = max(|u_R| + c) over both sides (Rusanov),
+// c^2 = gamma p/rho, or D/2 (matrix dissipation), or none (EC).
 // Logarithms are taken only on the log branch of a log-mean.
 template <int R>
 __device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const Cons &qp,
@@ -323,8 +395,15 @@ __device__ __forceinline__ void face_flux(const Node &a, const Cons &qm, const C
     const double hh = a.h0 * b.h0 + a.h1 * b.h1 + a.h2 * b.h2;
     const double cross = a.hp * hRb + b.hp * hRa;
     S[4] = frho * (izln * gm1i + 2.0 * hh + phi) + 2.0 * cross;
+    if (P.surf == SURF_MATRIX) {
+        double D[5];
+        matrix_dissipation<R>(a, b, rho_ln, izln, phi, P, D);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fn[v] = s * S[v] - 0.5 * D[v];
+        return;
+    }
     double hl = 0.0;
-    if (P.surf == 0) {
+    if (P.surf == SURF_RUSANOV) {
         const double la = 2.0 * fabs(hRa) + sqrt_pos(g * a.zi);
         const double lb = 2.0 * fabs(hRb) + sqrt_pos(g * b.zi);
         hl = 0.5 * (la > lb ? la : lb);

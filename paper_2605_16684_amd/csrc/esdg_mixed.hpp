@@ -166,6 +166,79 @@ __device__ __forceinline__ float sym_flux_mixed(const NodeF &a, const NodeF &b, 
     return rho_ln;
 }
 
+// Matrix dissipation (FP32), the operator of matrix_dissipation() with the
+// same averaged state and eigen-structure.  The jumps of z = rho/p, z u and
+// z |u|^2 / 2 are formed in FP64 from the two conservative states and then
+// rounded: an FP32 difference of the rounded z would carry an error of one
+// FP32 ulp of z, which the enthalpy h_hat ~ 1/{{z}}_log and phi scale up to
+// about 1e-4 of the energy flux.
+template <int R>
+__device__ __forceinline__ void matrix_dissipation_mixed(const NodeF &a, const NodeF &b,
+                                                         const Cons &qm, const Cons &qp,
+                                                         float rho_ln, float izln, double phi,
+                                                         double gm1, const StageParams &P,
+                                                         float D[5])
+{
+    constexpr int T1 = (R + 1) % 3, T2 = (R + 2) % 3;
+    const float g = (float)P.gamma, gm1i = (float)P.gm1i;
+    float dv[5];
+    {
+        // No FMA contraction here: the jumps are differences of products, and
+        // a contracted fma(x_b, y_b, -x_a y_a) leaves the rounding error of
+        // x_a y_a where the states are equal; the dissipation must vanish
+        // there exactly.
+#pragma clang fp contract(off)
+        double zj[2], zuj[2][3], kj[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const Cons &c = side ? qp : qm;
+            const double ri = frcp(c.v[0]);
+            const double mu = (c.v[1] * c.v[1] + c.v[2] * c.v[2] + c.v[3] * c.v[3]) * ri;
+            const double p = gm1 * (c.v[4] - 0.5 * mu - c.v[0] * phi);
+            const double ip = frcp(p);
+            zj[side] = c.v[0] * ip;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) zuj[side][d] = c.v[1 + d] * ip;
+            kj[side] = 0.5 * mu * ip;  // z |u|^2 / 2
+        }
+        const float dz = (float)(zj[1] - zj[0]);
+        dv[0] = (float)(qp.v[0] - qm.v[0]) * rcpf(rho_ln) + gm1i * (dz * izln) -
+                (float)(kj[1] - kj[0]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dv[1 + d] = (float)(zuj[1][d] - zuj[0][d]);
+        dv[4] = -dz;
+    }
+
+    const float u[3] = {a.h0 + b.h0, a.h1 + b.h1, a.h2 + b.h2};
+    const float ka = a.h0 * a.h0 + a.h1 * a.h1 + a.h2 * a.h2;
+    const float kb = b.h0 * b.h0 + b.h1 * b.h1 + b.h2 * b.h2;
+    const float u2bar = 2.0f * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 2.0f * (ka + kb);
+    const float phat = (a.r + b.r) * rcpf(a.z + b.z);
+    const float hhat = g * gm1i * izln + 0.5f * u2bar;
+    const float ahat = sqrtf(g * phat * rcpf(rho_ln));
+    const float un = u[R];
+    const float c0 = dv[0] + u[0] * dv[1] + u[1] * dv[2] + u[2] * dv[3] + hhat * dv[4];
+    const float an = ahat * (dv[1 + R] + un * dv[4]);
+    const float ta = rho_ln * (0.5f / g);
+    const float te = rho_ln * (g - 1.0f) / g;
+    const float aun = fabsf(un);
+    const float s0 = fabsf(un - ahat) * ta * (c0 - an);
+    const float s4 = fabsf(un + ahat) * ta * (c0 + an);
+    const float s1 = aun * te * (c0 - (hhat - 0.5f * u2bar) * dv[4]);
+    const float s2 = aun * phat * (dv[1 + T1] + u[T1] * dv[4]);
+    const float s3 = aun * phat * (dv[1 + T2] + u[T2] * dv[4]);
+    const float sa = s0 + s1 + s4, sd = s4 - s0;
+    D[0] = sa;
+    D[1] = u[0] * sa;
+    D[2] = u[1] * sa;
+    D[3] = u[2] * sa;
+    D[1 + R] += ahat * sd;
+    D[1 + T1] += s2;
+    D[1 + T2] += s3;
+    D[4] = hhat * (s0 + s4) + ahat * un * sd + 0.5f * u2bar * s1 + u[T1] * s2 + u[T2] * s3 +
+           (float)phi * sa;
+}
+
 // Face flux (FP32) with the perturbation pressure; the reference is
 // continuous across faces (and mirrored at walls), so p'+ uses the own
 // node's reference.  Jumps q+ - q- are formed in FP64.
@@ -191,13 +264,20 @@ __device__ __forceinline__ void face_flux_mixed(const NodeF &a, const Cons &qm, 
     const float hh = a.h0 * b.h0 + a.h1 * b.h1 + a.h2 * b.h2;
     const float cross = a.hp * hRb + b.hp * hRa;
     S[4] = frho * (izln * gm1i + 2.0f * hh + (float)phi) + 2.0f * cross;
+    const float sf = (float)s;
+    if (P.surf == SURF_MATRIX) {
+        float D[5];
+        matrix_dissipation_mixed<R>(a, b, qm, qp, rho_ln, izln, phi, gm1, P, D);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fn[v] = sf * S[v] - 0.5f * D[v];
+        return;
+    }
     float hl = 0.0f;
-    if (P.surf == 0) {
+    if (P.surf == SURF_RUSANOV) {
         const float la = 2.0f * fabsf(hRa) + sqrtf(g * a.zi);
         const float lb = 2.0f * fabsf(hRb) + sqrtf(g * b.zi);
         hl = 0.5f * (la > lb ? la : lb);
     }
-    const float sf = (float)s;
 #pragma unroll
     for (int v = 0; v < 5; ++v) Fn[v] = sf * S[v] - hl * (float)(qp.v[v] - qm.v[v]);
 }

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesdg.so")
 
 ESDG_OK, ESDG_EINVAL, ESDG_ENOMEM, ESDG_EHIP, ESDG_ENONPHYS, ESDG_ENOTIMPL = 0, -1, -2, -3, -4, -5
-SURF_RUSANOV, SURF_EC = 0, 1
+SURF_RUSANOV, SURF_EC, SURF_MATRIX = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 TERM_VOL, TERM_FACE, TERM_SRC, TERM_ALL = 1, 2, 4, 7
 

@@ -52,7 +52,7 @@ class MeshSpec:
     gas_R: float = GAS_R
     grav: float = GRAV
     coriolis_f: float = 0.0
-    surface_flux: int = 0  # 0 Rusanov, 1 entropy-conservative
+    surface_flux: int = 0  # 0 Rusanov, 1 entropy-conservative, 2 matrix dissipation
 
     @property
     def n_elem(self) -> int:

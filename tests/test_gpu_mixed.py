@@ -13,6 +13,8 @@ momentum of a perturbed hydrostatic state it is bounded too (the reference
 subtraction keeps it at the FP32 level of the perturbation, not of the full
 pressure).
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
@@ -77,6 +79,40 @@ def test_mixed_rhs_error(name, spec, kind):
         assert en[3] <= max(1e-5, 50 * 6e-8 * k[3] * 1e-3), en[3]
 
 
+def _with_jumps(q, seed):
+    """Seeded node-by-node perturbation so that states jump at every face."""
+    rng = np.random.default_rng(seed)
+    q = q.copy()
+    q *= (1.0 + 0.02 * rng.uniform(-1, 1, size=q[:, 0].shape))[:, None, :]
+    q[:, 1:4] += 5.0 * q[:, 0:1] * rng.uniform(-1, 1, size=q[:, 1:4].shape)
+    return q
+
+
+MATRIX_CASES = [
+    ("channel_N7_matrix", replace(W.channel(N=7, K=(4, 3, 2)).mesh, surface_flux=2), "channel"),
+    ("bubble_matrix", replace(W.rising_bubble(K=(4, 4, 4)).mesh, surface_flux=2), "bubble"),
+    ("N2_walls_matrix", W.MeshSpec(2, (3, 2, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (0, 0, 0),
+                                   surface_flux=2), "iso_pert"),
+]
+
+
+@pytest.mark.parametrize("jumps", [False, True], ids=["smooth", "jumps"])
+@pytest.mark.parametrize("name,spec,kind", MATRIX_CASES, ids=[c[0] for c in MATRIX_CASES])
+def test_mixed_rhs_error_matrix_dissipation(name, spec, kind, jumps):
+    om = _oracle_mesh(spec)
+    xyz = om.coords()
+    q = W.make_state(kind, xyz, spec, seed=5)
+    if jumps:
+        q = _with_jumps(q, 5)
+    r_or, g = om.rhs(q, gross=True)
+    m = _mixed_mesh(spec, xyz, kind)
+    r = m.rhs(torch.from_numpy(q).cuda()).cpu().numpy()
+    eg, en = err_gross(r, r_or, g), err_net(r, r_or)
+    print(f"[mixed {name} jumps={jumps}] err/gross={np.array2string(eg, precision=2)} "
+          f"err/net={np.array2string(en, precision=2)}", flush=True)
+    assert np.all(eg <= TOL_RHS_MIXED), eg
+
+
 def test_mixed_full_size_sampled_channel_N7():
     """The precision comparison's own configuration (160 x 24 x 10 channel
     at N = 7, 19.7 M nodes) in the launch configuration bench.py times:
@@ -110,8 +146,12 @@ def test_mixed_well_balanced_reference_state():
     assert np.all(err_gross(r, 0 * r, g) <= 1e-14)
 
 
-@pytest.mark.parametrize("name,wl", [("channel_N7_small", W.channel(N=7, K=(6, 4, 3))),
-                                     ("c0", W.iso_pert_cube())])
+@pytest.mark.parametrize("name,wl", [
+    ("channel_N7_small", W.channel(N=7, K=(6, 4, 3))),
+    ("c0", W.iso_pert_cube()),
+    ("channel_N4_matrix", replace(W.channel(K=(8, 4, 3)), mesh=replace(W.channel(K=(8, 4, 3)).mesh,
+                                                                        surface_flux=2))),
+])
 def test_mixed_100_steps_against_oracle(name, wl):
     spec = wl.mesh
     om = _oracle_mesh(spec)
