@@ -11,6 +11,7 @@ right-hand-side evaluations per second (DOF = N_e (N+1)^3 nodes; one step =
 Prints ONE JSON line on stdout (everything else goes to stderr).
 """
 import argparse
+from dataclasses import replace
 import json
 import os
 import sys
@@ -39,14 +40,14 @@ def traffic_record(kernel_name, workload):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, seconds, seed=1):
+def cpu_baseline(wl, spec, seconds, seed=1):
     """The oracle (plain FP64 C, OpenMP, full ordered-pair loop) timed on a
     bounded sample of the same workload: RHS evaluations of a fixed block of
     elements, repeated for about `seconds`."""
     import numpy as np
     import oracle as O
     from paper_2605_16684_amd import workloads as W
-    s = wl.mesh
+    s = spec
     om = O.Mesh(s.N, s.K, s.lo, s.hi, s.periodic, gamma=s.gamma, gas_R=s.gas_R, grav=s.grav,
                 coriolis_f=s.coriolis_f, surface_flux=s.surface_flux)
     q = W.make_state(wl.kind, om.coords(), s, seed=seed)
@@ -185,6 +186,42 @@ def serving_block(torch, throughput, n=96, steps=50, budget_gb=24.0, load=1.2, s
     return out
 
 
+def surface_block(esdg, torch, spec, q, dt, steps, epw, value, t_rhs):
+    """The same workload and state with matrix-dissipation faces (the paper's
+    interface flux): whole LSRK(5,4) steps and RHS-only launches, beside the
+    Rusanov figures of the headline run."""
+    stream = torch.cuda.current_stream()
+    m = esdg.Mesh(replace(spec, surface_flux=esdg.SURF_MATRIX), epw=epw)
+    qm = q.clone()
+    dq = torch.zeros_like(qm)
+    m.lsrk_run(qm, dq, dt, 2)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    m.lsrk_run(qm, dq, dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    m.check()
+    r = torch.empty_like(qm)
+    for _ in range(3):
+        m.rhs(qm, r)
+    nr = 20
+    e0.record(stream)
+    for _ in range(nr):
+        m.rhs(qm, r)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_r = e0.elapsed_time(e1) * 1e-3 / nr
+    nn = m.n_nodes
+    v = nn * 5.0 * steps / (ms * 1e-3)
+    m.close()
+    return {"surface_flux": "matrix dissipation", "steps": steps, "ms_per_step": ms / steps,
+            "dof_rhs_per_s": v, "vs_rusanov": v / value,
+            "rhs_only_launch_ms": t_r * 1e3, "rhs_only_vs_rusanov": t_rhs / t_r}
+
+
 def sweep_block(esdg, W, torch, orders=(3, 4, 5, 7), sizes=(2, 4, 8, 12, 16, 24, 32, 40),
                 max_nodes=4.0e7, steps=6):
     """Throughput against mesh size per order: LSRK steps on rising-bubble
@@ -231,6 +268,10 @@ def main():
     ap.add_argument("--precision-workload", default="c3")
     ap.add_argument("--no-serving", action="store_true", help="skip the ensemble serving run")
     ap.add_argument("--serving-requests", type=int, default=96)
+    ap.add_argument("--surface", default="rusanov", choices=("rusanov", "matrix", "ec"),
+                    help="interface dissipation of the headline run")
+    ap.add_argument("--no-matrix-leg", action="store_true",
+                    help="skip the matrix-dissipation run beside a Rusanov headline")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure throughput against mesh size for N in 3, 4, 5, 7")
     ap.add_argument("--calib-copy", action="store_true",
@@ -251,7 +292,9 @@ def main():
     from paper_2605_16684_amd import workloads as W
 
     wl = W.WORKLOADS[args.workload]
-    spec = wl.mesh
+    surf_code = {"rusanov": esdg.SURF_RUSANOV, "ec": esdg.SURF_EC,
+                 "matrix": esdg.SURF_MATRIX}[args.surface]
+    spec = replace(wl.mesh, surface_flux=surf_code)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
 
@@ -294,7 +337,8 @@ def main():
     achieved_gbs = bytes_launch / t_launch / 1e9
     achieved_tf = flops_launch / t_launch / 1e12
     kname = f"stage_fp64<{N + 1},{mesh.epw}>"
-    traffic = traffic_record("stage_fp64", wl.name)
+    traffic = traffic_record("stage_fp64", wl.name if args.surface == "rusanov"
+                             else f"{wl.name}_{args.surface}")
 
     # RHS-only launches (no update), for the per-kernel table
     r = torch.empty_like(q)
@@ -347,7 +391,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "N": N, "K": list(spec.K), "n_elem": mesh.n_elem,
-                   "nodes": nn, "dt": dt, "cfl": wl.cfl, "surface_flux": "rusanov",
+                   "nodes": nn, "dt": dt, "cfl": wl.cfl, "surface_flux": args.surface,
                    "epw": mesh.epw, "step": "5 fused stage kernels (hipGraph)"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": perfmodel.HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved_gbs / perfmodel.HBM_PEAK_GBS,
@@ -368,7 +412,12 @@ def main():
         "cpu_baseline": None,
     }
     mesh.close()
-    del q, dq, r
+    del dq, r
+    if args.surface == "rusanov" and not args.no_matrix_leg:
+        log("[bench] matrix-dissipation faces ...")
+        out["surface_matrix"] = surface_block(esdg, torch, spec, q, dt, 2 * max(1, min(K, 40) // 2),
+                                              args.epw, value, t_rhs)
+    del q
     torch.cuda.empty_cache()
     if not args.no_precision:
         log("[bench] FP64 vs FP32-mixed ...")
@@ -383,7 +432,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("[bench] timing the CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, spec, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
