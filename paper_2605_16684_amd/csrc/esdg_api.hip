@@ -284,6 +284,22 @@ int default_epw(int N)
     }
 }
 
+// The default of one precision: the measured FP64 choice where that
+// precision compiles it, else its first compiled variant for N.
+int default_epw(int N, int precision)
+{
+    const int e = default_epw(N);
+    if (has_variant(precision, N, e)) return e;
+    if (precision == ESDG_FP32_MIXED) {
+        for (const MixedVariant &v : kMixedVariants)
+            if (v.N == N) return v.epw;
+    } else {
+        for (const Variant &v : kVariants)
+            if (v.N == N) return v.epw;
+    }
+    return e;
+}
+
 GeomParams geom(const esdg_mesh *m)
 {
     GeomParams G;
@@ -552,7 +568,7 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         if ((rc0 = check_ptr(d->ref_rho, "ref_rho")) || (rc0 = check_ptr(d->ref_p, "ref_p")))
             return rc0;
     }
-    const int epw = d->epw ? d->epw : default_epw(d->N);
+    const int epw = d->epw ? d->epw : default_epw(d->N, d->precision);
     if (!has_variant(d->precision, d->N, epw))
         return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", d->N, epw);
     int dev = 0;
@@ -650,7 +666,7 @@ int esdg_set_epw(esdg_mesh_t m, int32_t epw)
 {
     int rc = check_mesh(m);
     if (rc) return rc;
-    const int e = epw ? epw : default_epw(m->N);
+    const int e = epw ? epw : default_epw(m->N, m->desc.precision);
     if (!has_variant(m->desc.precision, m->N, e))
         return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", m->N, e);
     m->epw = e;

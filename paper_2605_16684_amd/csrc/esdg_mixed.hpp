@@ -86,17 +86,49 @@ __device__ __forceinline__ float inv_log_mean_f(float a, float b, float la, floa
     return ser ? 2.0f * r * (1.0f + u * (IF1 + u * (IF2 + u * (IF3 + u * IF4)))) : (lb - la) * r;
 }
 
-// {{rho}}_log - {{rho_r}}_log from the perturbations rho' (both pairs in the
-// series branch):  L = s g(u)/2,  L - L_r = (s - s_r) g(u)/2 + s_r (g(u) - g(u_r))/2,
-// g(u) - g(u_r) = -(u - u_r) [1/3 + 4(u+u_r)/45 + 44(u^2+u u_r+u_r^2)/945],
-// u - u_r = (f - f_r)(f + f_r),  f - f_r = (d' s_r - d_r s') / (s s_r).
-// Outside the series branch the difference is formed in FP64.
+// {{rho}}_log - {{rho_r}}_log from the perturbations rho', in one of three
+// forms, none of which subtracts two nearly equal FP32 numbers:
+//  - both pairs in the series branch:  L = s g(u)/2,
+//    L - L_r = (s - s_r) g(u)/2 + s_r (g(u) - g(u_r))/2,
+//    g(u) - g(u_r) = -(u - u_r) [1/3 + 4(u+u_r)/45 + 44(u^2+u u_r+u_r^2)/945],
+//    u - u_r = (f - f_r)(f + f_r),  f - f_r = (d' s_r - d_r s') / (s s_r);
+//  - both pairs in the log branch: with l = [[ln rho]], l_r = [[ln rho_r]]
+//    and l' = l - l_r = [[ln(1 + x)]], x = rho'/rho_r,
+//    L - L_r = (d + d')/(l_r + l') - d_r/l_r = (d' l_r - d_r l') / (l l_r),
+//    whose numerator holds only perturbation-sized products; l' is one
+//    log1p of the relative jump (x_b - x_a)/(1 + x_a), l comes from the
+//    per-node logs of rho and l_r = l - l' (|l|, |l_r| >= 0.2 outside the
+//    series range);
+//  - one pair in each branch (a perturbation as large as the reference's
+//    own variation over the pair): FP64.
+// At N = 5 the kernel holds 250 of the 256 registers that keep two waves per
+// SIMD, and the FP32 log-branch form's per-node temporaries would cost it a
+// wave: there both log-branch cases take the FP64 form.
+template <int NQ>
+constexpr bool fp32_log_branch()
+{
+    return NQ != 6;
+}
+
+template <int NQ>
 __device__ __forceinline__ float dlog_mean_f(const NodeF &a, const NodeF &b)
 {
     const float dr = b.rr - a.rr, sr = a.rr + b.rr;
     const float dp = b.rp - a.rp, sp = a.rp + b.rp;
     const float d = dr + dp, s = sr + sp;
-    if (fabsf(d) < LMF_SQRT * s && fabsf(dr) < LMF_SQRT * sr) {
+    const bool ser = fabsf(d) < LMF_SQRT * s, ser_r = fabsf(dr) < LMF_SQRT * sr;
+    if (fp32_log_branch<NQ>() && !ser && !ser_r) {
+        const float xa = a.rp * rcpf(a.rr), xb = b.rp * rcpf(b.rr);
+        const float y = (xb - xa) * rcpf(1.0f + xa);
+        // ln(1 + y) to a few ulp also for small y: the rounding of 1 + y is
+        // undone by the factor y / ((1 + y) - 1)
+        const float u1 = 1.0f + y;
+        const float lp = (u1 == 1.0f) ? y : lnf(u1) * (y * rcpf(u1 - 1.0f));
+        const float l = b.lr - a.lr;
+        const float l_r = l - lp;
+        return (dp * l_r - dr * lp) * rcpf(l * l_r);
+    }
+    if (ser && ser_r) {
         const float rs = rcpf(s), rsr = rcpf(sr);
         const float f = d * rs, fr = dr * rsr;
         const float u = f * f, ur = fr * fr;
@@ -369,7 +401,7 @@ __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const Ord
                     // B - B_r = B_r (beta_b - beta_a)/(1 + beta_a); partner likewise
                     // with a and b exchanged and [[phi]] negated.
                     const float dphi = (float)(phi_k[b] - phi_k[a]);
-                    const float dL = dlog_mean_f(nd[a], nd[b]);
+                    const float dL = dlog_mean_f<NQ>(nd[a], nd[b]);
                     const float Br = nd[b].zr * nd[a].izr;
                     const float Bri = nd[a].zr * nd[b].izr;
                     const float dB = Br * (nd[b].beta - nd[a].beta) * nd[a].ib1;

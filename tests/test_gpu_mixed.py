@@ -56,7 +56,25 @@ CASES = [
     ("N3_walls", W.MeshSpec(3, (3, 2, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (0, 0, 0)), "iso_pert"),
     ("N5_ec", W.MeshSpec(5, (2, 2, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 0, 0),
                          surface_flux=1), "iso_pert"),
+    ("N6_walls", W.MeshSpec(6, (2, 1, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (0, 1, 0)),
+     "iso_pert"),
+    ("channel_small_N6", W.channel(N=6, K=(4, 3, 2)).mesh, "channel"),
 ]
+
+
+@pytest.mark.parametrize("N", range(1, 9))
+def test_default_epw_exists_for_every_order(N):
+    # a mesh created with epw = 0 gets a compiled variant of its own
+    # precision, and set_epw(0) returns to it
+    esdg = _esdg()
+    spec = W.MeshSpec(N, (2, 1, 1), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 1, 0))
+    xyz = _oracle_mesh(spec).coords()
+    for m in (esdg.Mesh(spec), _mixed_mesh(spec, xyz, "iso_pert")):
+        e = m.epw
+        assert e in esdg.epw_options(N, m.precision)
+        m.set_epw(0)
+        assert m.epw == e
+        m.close()
 
 
 @pytest.mark.parametrize("name,spec,kind", CASES, ids=[c[0] for c in CASES])
