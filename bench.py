@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP64 vs FP32-mixed comparison")
     ap.add_argument("--precision-workload", default="c3")
+    ap.add_argument("--precision-steps", type=int, default=100,
+                    help="LSRK steps of each precision in the FP64 vs FP32-mixed run")
     ap.add_argument("--no-serving", action="store_true", help="skip the ensemble serving run")
     ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--surface", default="rusanov", choices=("rusanov", "matrix", "ec"),
@@ -421,7 +423,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_precision:
         log("[bench] FP64 vs FP32-mixed ...")
-        out["precision"] = precision_block(esdg, W, torch, workload=args.precision_workload)
+        out["precision"] = precision_block(esdg, W, torch, steps=args.precision_steps,
+                                           workload=args.precision_workload)
         torch.cuda.empty_cache()
     if args.sweep:
         log("[bench] size sweep ...")

@@ -162,6 +162,39 @@ def cmd_flops(a):
     print(txt)
 
 
+def cmd_mix(a):
+    """Instruction mix per wave of the stage kernels, from one or more
+    counter passes of the same command (each pass counts SQ_WAVES too)."""
+    per = {}
+    for db in a.dbs:
+        waves = counter_by_kernel(db, "SQ_WAVES")
+        for row in _rows(db, "select distinct counter_name from counters_collection"):
+            c = row[0]
+            if c == "SQ_WAVES":
+                continue
+            for name, vals in counter_by_kernel(db, c).items():
+                if "stage_" not in name or name not in waves:
+                    continue
+                w = sum(waves[name]) / len(waves[name])
+                per.setdefault(name, {})[c] = sum(vals) / len(vals) / w
+    counters = sorted({c for r in per.values() for c in r})
+    names = sorted(per)
+    lines = [f"# Instruction mix per wave: {a.workload}", "", "Commands (one counter pass each):",
+             "", "```", *a.cmd, "```", "",
+             "Average count per wave over the launches of each kernel (SQ counters divided by "
+             "SQ_WAVES of the same pass).", "",
+             "| counter | " + " | ".join(f"`{n[:48]}`" for n in names) + " |",
+             "|---|" + "---:|" * len(names)]
+    for c in counters:
+        lines.append(f"| {c} | " + " | ".join(
+            f"{per[n][c]:.0f}" if c in per[n] else "" for n in names) + " |")
+    txt = "\n".join(lines) + "\n"
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
+    print(txt)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -189,6 +222,12 @@ def main(argv=None):
     f.add_argument("--cmd-trace", required=True)
     f.add_argument("--out")
     f.set_defaults(fn=cmd_flops)
+    m = sub.add_parser("mix")
+    m.add_argument("dbs", nargs="+")
+    m.add_argument("--workload", required=True)
+    m.add_argument("--cmd", action="append", required=True)
+    m.add_argument("--out")
+    m.set_defaults(fn=cmd_mix)
     a = ap.parse_args(argv)
     a.fn(a)
 
