@@ -35,6 +35,12 @@ def _load():
         "oracle_lgl": (None, [C.c_int, _dp, _dp, _dp]),
         "oracle_mesh_create": (C.c_void_p, [C.c_int, _ip, _dp, _dp, _ip, C.c_double,
                                             C.c_double, C.c_double, C.c_double, C.c_int]),
+        "oracle_mesh_create_warped": (C.c_void_p, [C.c_int, _ip, _dp, _dp, _ip, C.c_double,
+                                                   C.c_double, C.c_double, C.c_double, C.c_int,
+                                                   _dp]),
+        "oracle_metrics": (None, [C.c_void_p, _dp, _dp]),
+        "oracle_surface_flux_vec": (None, [_dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                           C.c_int, _dp]),
         "oracle_mesh_destroy": (None, [C.c_void_p]),
         "oracle_mesh_nelem": (C.c_int64, [C.c_void_p]),
         "oracle_node_coords": (None, [C.c_void_p, _dp]),
@@ -118,6 +124,13 @@ def surface_flux(r, s, qm, qp, phim, phip, gamma=1.4, surf=SURF_RUSANOV):
     return out
 
 
+def surface_flux_vec(Nv, qm, qp, phim, phip, gamma=1.4, surf=SURF_RUSANOV):
+    out = np.zeros(5)
+    _lib.oracle_surface_flux_vec(_ptr(_vec(Nv, 3)), _ptr(_vec(qm)), _ptr(_vec(qp)), phim, phip,
+                                 gamma, surf, _ptr(out))
+    return out
+
+
 def entropy_vars(q, phi, gamma=1.4):
     out = np.zeros(5)
     _lib.oracle_entropy_vars(_ptr(_vec(q)), phi, gamma, _ptr(out))
@@ -152,7 +165,7 @@ class Mesh:
     """Uniform box of K[0] x K[1] x K[2] affine hexahedra of order N."""
 
     def __init__(self, N, K, lo, hi, periodic, gamma=1.4, gas_R=287.0, grav=9.81,
-                 coriolis_f=0.0, surface_flux=SURF_RUSANOV):
+                 coriolis_f=0.0, surface_flux=SURF_RUSANOV, warp=None):
         self.N, self.Nq, self.Np = N, N + 1, (N + 1) ** 3
         self.K = tuple(int(k) for k in K)
         self.lo, self.hi = tuple(map(float, lo)), tuple(map(float, hi))
@@ -163,8 +176,14 @@ class Mesh:
         Pa = (C.c_int * 3)(*self.periodic)
         lo_a = (C.c_double * 3)(*self.lo)
         hi_a = (C.c_double * 3)(*self.hi)
-        self._h = _lib.oracle_mesh_create(N, Ka, lo_a, hi_a, Pa, gamma, gas_R, grav,
-                                          coriolis_f, surface_flux)
+        self.warp = None if warp is None else tuple(map(float, warp))
+        if warp is None:
+            self._h = _lib.oracle_mesh_create(N, Ka, lo_a, hi_a, Pa, gamma, gas_R, grav,
+                                              coriolis_f, surface_flux)
+        else:
+            wa = (C.c_double * 3)(*self.warp)
+            self._h = _lib.oracle_mesh_create_warped(N, Ka, lo_a, hi_a, Pa, gamma, gas_R, grav,
+                                                     coriolis_f, surface_flux, wa)
         if not self._h:
             raise ValueError("oracle_mesh_create rejected the mesh description")
         self.ne = int(_lib.oracle_mesh_nelem(self._h))
@@ -188,6 +207,14 @@ class Mesh:
         xyz = np.zeros((self.ne, 3, self.Np))
         _lib.oracle_node_coords(self._h, _ptr(xyz))
         return xyz
+
+    def metrics(self):
+        """Curved meshes: (Ja [e][r][d][n], J [e][n]) -- J a^r_d and J."""
+        assert self.warp is not None
+        Ja = np.zeros((self.ne, 3, 3, self.Np))
+        Jd = np.zeros((self.ne, self.Np))
+        _lib.oracle_metrics(self._h, _ptr(Ja), _ptr(Jd))
+        return Ja, Jd
 
     def phi(self):
         out = np.zeros((self.ne, self.Np))

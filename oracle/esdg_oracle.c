@@ -38,6 +38,11 @@
  *     paper's choice, Sec. 3, whose formula it cites but does not print);
  *   - reflecting walls: mirror state (rho, m - 2 (m.n) n, E), phi+ = phi-;
  *   - Coriolis: f-plane, h = (0, f m_y, -f m_x, 0, 0);
+ *   - curved hexahedra (oracle_mesh_create_warped): the box warped by a
+ *     smooth displacement that vanishes on the box faces; metric terms in
+ *     Kopriva's conservative curl form, volume flux with averaged metrics,
+ *     face flux along the contravariant normal (Sec. 3: the metric terms G
+ *     and the surface terms of the semi-discrete form);
  *   - time step: dt = CFL / ((N+1) max_a sum_r (|u_r| + c) / h_r).
  */
 #include <math.h>
@@ -69,6 +74,9 @@ typedef struct {
     int64_t ne, nn;
     double *xyz; /* [e][3][Np] node coordinates */
     double *phi; /* [e][Np] geopotential at the nodes */
+    /* curved meshes only (NULL for the affine box): */
+    double *Ja;  /* [e][r][d][Np] J a^r_d, the contravariant basis times J */
+    double *Jd;  /* [e][Np] Jacobian determinant J */
 } omesh;
 
 /* ------------------------------------------------------------------------ */
@@ -230,7 +238,133 @@ void oracle_mesh_destroy(void *mp)
     if (!m) return;
     free(m->xyz);
     free(m->phi);
+    free(m->Ja);
+    free(m->Jd);
     free(m);
+}
+
+/* sin(2 pi k s), exactly 0 at s = 0 and s = 1 (the box faces). */
+static double sin2pik(int k, double s)
+{
+    if (s == 0.0 || s == 1.0) return 0.0;
+    return sin(2.0 * 3.14159265358979323846 * k * s);
+}
+
+/* Derivative along reference direction j of the nodal field f of one
+ * element, at node n: sum_l D[i_j(n)][l] f(n with i_j = l). */
+static double dref(const omesh *m, const double *f, int n, int j)
+{
+    const int Nq = m->Nq;
+    int ii[3] = {n % Nq, (n / Nq) % Nq, n / (Nq * Nq)};
+    double acc = 0.0;
+    for (int l = 0; l < Nq; ++l) {
+        int jj[3] = {ii[0], ii[1], ii[2]};
+        jj[j] = l;
+        acc += m->D[ii[j]][l] * f[jj[0] + Nq * (jj[1] + Nq * jj[2])];
+    }
+    return acc;
+}
+
+/* Metric terms of one element from its nodal coordinates X (Sec. 3, the
+ * metric terms G of the semi-discrete form), in the conservative curl form
+ *   J a^i_n = -e_i . curl_xi( X_l grad_xi X_m ),   (n, m, l) cyclic,
+ * with every derivative the LGL derivative D.  This form satisfies the
+ * discrete metric identities sum_i d/dxi_i (J a^i_n) = 0, which keep a
+ * uniform flow uniform.  J = det(dX/dxi). */
+static void element_metrics(const omesh *m, int64_t e, double *Ja, double *Jd)
+{
+    const int Np = m->Np;
+    const double *X[3];
+    for (int d = 0; d < 3; ++d) X[d] = m->xyz + (e * 3 + d) * Np;
+    double *dX = (double *)malloc(sizeof(double) * 9 * Np); /* [m][j][n] */
+    double *Y = (double *)malloc(sizeof(double) * 3 * Np);  /* [j][n] */
+    for (int mm = 0; mm < 3; ++mm)
+        for (int j = 0; j < 3; ++j)
+            for (int n = 0; n < Np; ++n) dX[(mm * 3 + j) * Np + n] = dref(m, X[mm], n, j);
+    for (int n = 0; n < Np; ++n) {
+        const double *a0 = dX, *a1 = dX + 3 * Np, *a2 = dX + 6 * Np;
+        /* rows: d X_0/d xi_j, d X_1/d xi_j, d X_2/d xi_j */
+        double A[3][3];
+        for (int j = 0; j < 3; ++j) {
+            A[0][j] = a0[j * Np + n];
+            A[1][j] = a1[j * Np + n];
+            A[2][j] = a2[j * Np + n];
+        }
+        Jd[n] = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    }
+    for (int nn = 0; nn < 3; ++nn) {
+        int mm = (nn + 1) % 3, l = (nn + 2) % 3;
+        for (int j = 0; j < 3; ++j)
+            for (int n = 0; n < Np; ++n) Y[j * Np + n] = X[l][n] * dX[(mm * 3 + j) * Np + n];
+        for (int i = 0; i < 3; ++i) {
+            int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+            for (int n = 0; n < Np; ++n) {
+                double curl = dref(m, Y + i2 * Np, n, i1) - dref(m, Y + i1 * Np, n, i2);
+                Ja[(i * 3 + nn) * Np + n] = -curl;
+            }
+        }
+    }
+    free(dX);
+    free(Y);
+}
+
+/* Curved mesh: the box of oracle_mesh_create with every node displaced by
+ *   X_d = x_d + warp_d L_d prod_c sin(2 pi k_dc s_c),   s = (x - lo)/L,
+ * k_dc = 2 for c = d > 0 and 1 otherwise (each coordinate gets a field of
+ * its own, so that the metric terms are not the special case of a
+ * displacement along one fixed direction).  The displacement vanishes on
+ * the box faces, so walls stay planar and periodic faces still match;
+ * interior faces are curved.  With warp = (0, 0, 0) the curved code path
+ * runs on the affine box. */
+void *oracle_mesh_create_warped(int N, const int *K, const double *lo, const double *hi,
+                                const int *periodic, double gamma, double gas_R, double grav,
+                                double cor_f, int surf, const double *warp)
+{
+    if (surf == SURF_MATRIX) return NULL; /* general-normal matrix dissipation: not built */
+    omesh *m = (omesh *)oracle_mesh_create(N, K, lo, hi, periodic, gamma, gas_R, grav, cor_f,
+                                           surf);
+    if (!m) return NULL;
+    const int Np = m->Np;
+    m->Ja = (double *)malloc(sizeof(double) * 9 * m->nn);
+    m->Jd = (double *)malloc(sizeof(double) * m->nn);
+    if (!m->Ja || !m->Jd) {
+        oracle_mesh_destroy(m);
+        return NULL;
+    }
+    double L[3];
+    for (int d = 0; d < 3; ++d) L[d] = hi[d] - lo[d];
+    for (int64_t e = 0; e < m->ne; ++e)
+        for (int n = 0; n < Np; ++n) {
+            double x[3], sv[3];
+            for (int c = 0; c < 3; ++c) {
+                x[c] = m->xyz[(e * 3 + c) * Np + n];
+                sv[c] = (x[c] - lo[c]) / L[c];
+            }
+            for (int d = 0; d < 3; ++d) {
+                double sn = 1.0;
+                for (int c = 0; c < 3; ++c) sn *= sin2pik((c == d && d > 0) ? 2 : 1, sv[c]);
+                m->xyz[(e * 3 + d) * Np + n] = x[d] + warp[d] * L[d] * sn;
+            }
+            m->phi[e * Np + n] = grav * m->xyz[(e * 3 + 2) * Np + n];
+        }
+    for (int64_t e = 0; e < m->ne; ++e)
+        element_metrics(m, e, m->Ja + e * 9 * Np, m->Jd + e * Np);
+    for (int64_t i = 0; i < m->nn; ++i)
+        if (!(m->Jd[i] > 0.0)) {
+            oracle_mesh_destroy(m);
+            return NULL;
+        }
+    return m;
+}
+
+void oracle_metrics(void *mp, double *Ja, double *Jd)
+{
+    omesh *m = (omesh *)mp;
+    if (!m->Ja) return;
+    memcpy(Ja, m->Ja, sizeof(double) * 9 * m->nn);
+    memcpy(Jd, m->Jd, sizeof(double) * m->nn);
 }
 
 int64_t oracle_mesh_nelem(void *mp) { return ((omesh *)mp)->ne; }
@@ -456,6 +590,34 @@ void oracle_surface_flux(int r, int s, const double qm[5], const double qp[5], d
     for (int v = 0; v < 5; ++v) Fn[v] = s * F[v] - 0.5 * lam * (qp[v] - qm[v]);
 }
 
+/* Face flux along a general (unnormalised) normal Nv = s J a^r of a curved
+ * element: sum_d Nv_d f_d(q-, q+) minus the Rusanov dissipation
+ * |Nv| lambda/2 (q+ - q-), lambda = max(|u.n| + c) with n = Nv/|Nv|, or
+ * without dissipation (EC).  Faces have phi+ = phi-. */
+void oracle_surface_flux_vec(const double Nv[3], const double qm[5], const double qp[5],
+                             double phim, double phip, double gamma, int surf, double Fn[5])
+{
+    for (int v = 0; v < 5; ++v) Fn[v] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double F[5];
+        oracle_two_point_flux(d, qm, qp, phim, phip, gamma, F);
+        for (int v = 0; v < 5; ++v) Fn[v] += Nv[d] * F[v];
+    }
+    if (surf != SURF_RUSANOV) return;
+    double nrm = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+    double lam = 0.0;
+    const double *qs[2] = {qm, qp};
+    double phis[2] = {phim, phip};
+    for (int t = 0; t < 2; ++t) {
+        const double *q = qs[t];
+        double p = pressure(q, phis[t], gamma);
+        double un = (q[1] * Nv[0] + q[2] * Nv[1] + q[3] * Nv[2]) / (q[0] * nrm);
+        double l = fabs(un) + sqrt(gamma * p / q[0]);
+        if (l > lam) lam = l;
+    }
+    for (int v = 0; v < 5; ++v) Fn[v] -= 0.5 * lam * nrm * (qp[v] - qm[v]);
+}
+
 /* Entropy variables of eta = -rho s/(gamma-1), s = ln p - gamma ln rho, for
  * total energy including rho*phi:
  * v = ((gamma - s)/(gamma-1) - b|u|^2 + 2 b phi, 2 b u, -2 b), b = rho/(2p). */
@@ -525,6 +687,84 @@ static void plus_state(const omesh *m, const double *q, int64_t e, const int ee[
     *phip = m->phi[en * Np + nn];
 }
 
+/* R for one element of a curved mesh: the skew form with averaged metrics,
+ *   R_a = h_a - (1/J_a) sum_r (1/w_{i_r(a)}) sum_{b on the r-line of a}
+ *                 S_{i_r(a) i_r(b)} sum_d {{J a^r_d}}_ab F_d(a, b)
+ *         - sum over faces of a: (1/(J_a w_0)) F*(q_a, q+; s J a^r(a)),
+ * where F_d is the two-point flux of direction d (gravity term included) and
+ * {{.}}_ab the average of the two nodes' metric terms.  On the affine box
+ * J a^r_d = J (2/h_r) delta_rd and this is rhs_element's sum. */
+static void rhs_element_curved(const omesh *m, const double *q, double *R, double *gross,
+                               int64_t e, int mask)
+{
+    const int N = m->N, Nq = m->Nq, Np = m->Np;
+    int ee[3];
+    ee[0] = (int)(e % m->K[0]);
+    ee[1] = (int)((e / m->K[0]) % m->K[1]);
+    ee[2] = (int)(e / ((int64_t)m->K[0] * m->K[1]));
+    const double *Ja = m->Ja + e * 9 * Np;
+    for (int a = 0; a < Np; ++a) {
+        int ii[3] = {a % Nq, (a / Nq) % Nq, a / (Nq * Nq)};
+        double qa[5], acc[5] = {0, 0, 0, 0, 0}, gacc[5] = {0, 0, 0, 0, 0};
+        load_node(q, e, Np, a, qa);
+        double phia = m->phi[e * Np + a];
+        double iJ = 1.0 / m->Jd[e * Np + a];
+        if (mask & TERM_VOL) {
+            for (int r = 0; r < 3; ++r) {
+                int ia = ii[r];
+                for (int l = 0; l < Nq; ++l) {
+                    if (l == ia) continue;
+                    int jj[3] = {ii[0], ii[1], ii[2]};
+                    jj[r] = l;
+                    int b = jj[0] + Nq * (jj[1] + Nq * jj[2]);
+                    double qb[5], Ft[5] = {0, 0, 0, 0, 0};
+                    load_node(q, e, Np, b, qb);
+                    for (int d = 0; d < 3; ++d) {
+                        double F[5];
+                        oracle_two_point_flux(d, qa, qb, phia, m->phi[e * Np + b], m->gamma, F);
+                        double jav = 0.5 * (Ja[(r * 3 + d) * Np + a] + Ja[(r * 3 + d) * Np + b]);
+                        for (int v = 0; v < 5; ++v) Ft[v] += jav * F[v];
+                    }
+                    double coef = -iJ * m->S[ia][l] / m->w[ia];
+                    for (int v = 0; v < 5; ++v) {
+                        acc[v] += coef * Ft[v];
+                        gacc[v] += fabs(coef * Ft[v]);
+                    }
+                }
+            }
+        }
+        if (mask & TERM_FACE) {
+            for (int r = 0; r < 3; ++r) {
+                int sides[2] = {0, 0}, ns = 0;
+                if (ii[r] == 0) sides[ns++] = -1;
+                if (ii[r] == N) sides[ns++] = +1;
+                for (int t = 0; t < ns; ++t) {
+                    int s = sides[t];
+                    double qp[5], phip, Fn[5], Nv[3];
+                    plus_state(m, q, e, ee, ii, r, s, qp, &phip);
+                    for (int d = 0; d < 3; ++d) Nv[d] = s * Ja[(r * 3 + d) * Np + a];
+                    oracle_surface_flux_vec(Nv, qa, qp, phia, phip, m->gamma, m->surf, Fn);
+                    double coef = -iJ / m->w[ii[r]];
+                    for (int v = 0; v < 5; ++v) {
+                        acc[v] += coef * Fn[v];
+                        gacc[v] += fabs(coef * Fn[v]);
+                    }
+                }
+            }
+        }
+        if (mask & TERM_SRC) {
+            acc[1] += m->cor_f * qa[2];
+            acc[2] -= m->cor_f * qa[1];
+            gacc[1] += fabs(m->cor_f * qa[2]);
+            gacc[2] += fabs(m->cor_f * qa[1]);
+        }
+        for (int v = 0; v < 5; ++v) {
+            R[(e * 5 + v) * Np + a] = acc[v];
+            if (gross) gross[(e * 5 + v) * Np + a] = gacc[v];
+        }
+    }
+}
+
 /* R for one element in the skew (flux-differencing) form that the printed
  * semi-discrete equation (nm:semi) stands for on affine hexahedra:
  *   R_a = h_a - sum_r (2/h_r)(1/w_{i_r(a)}) sum_{b on the r-line of a}
@@ -536,6 +776,10 @@ static void plus_state(const omesh *m, const double *q, int64_t e, const int ee[
 static void rhs_element(const omesh *m, const double *q, double *R, double *gross,
                         int64_t e, int mask)
 {
+    if (m->Ja) {
+        rhs_element_curved(m, q, R, gross, e, mask);
+        return;
+    }
     const int N = m->N, Nq = m->Nq, Np = m->Np;
     int ee[3];
     ee[0] = (int)(e % m->K[0]);
@@ -633,6 +877,7 @@ int oracle_rhs_elems(void *mp, const double *q, double *R, double *gross, int ma
 int oracle_rhs_strong(void *mp, const double *q, double *R)
 {
     omesh *m = (omesh *)mp;
+    if (m->Ja) return -1; /* affine boxes only */
     const int N = m->N, Nq = m->Nq, Np = m->Np;
     for (int64_t e = 0; e < m->ne; ++e) {
         int ee[3];
@@ -813,7 +1058,8 @@ int oracle_entropy(void *mp, const double *q, double *out)
     for (int64_t e = 0; e < m->ne; ++e)
         for (int a = 0; a < Np; ++a) {
             int i = a % Nq, j = (a / Nq) % Nq, k = a / (Nq * Nq);
-            double wq = J * m->w[i] * m->w[j] * m->w[k];
+            double Jn = m->Jd ? m->Jd[e * Np + a] : J;
+            double wq = Jn * m->w[i] * m->w[j] * m->w[k];
             double qa[5], v[5];
             load_node(q, e, Np, a, qa);
             double phi = m->phi[e * Np + a];
@@ -846,7 +1092,21 @@ double oracle_cfl_dt(void *mp, const double *q, double cfl)
             double p = pressure(qa, m->phi[e * Np + a], m->gamma);
             double c = sqrt(m->gamma * p / qa[0]);
             double s = 0.0;
-            for (int r = 0; r < 3; ++r) s += (fabs(qa[1 + r] / qa[0]) + c) / m->h[r];
+            if (m->Ja) {
+                /* (|u . J a^r| + c |J a^r|) / (2 J): the affine (|u_r| + c) / h_r */
+                const double *Ja = m->Ja + e * 9 * Np;
+                for (int r = 0; r < 3; ++r) {
+                    double un = 0.0, n2 = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        double jv = Ja[(r * 3 + d) * Np + a];
+                        un += qa[1 + d] / qa[0] * jv;
+                        n2 += jv * jv;
+                    }
+                    s += (fabs(un) + c * sqrt(n2)) / (2.0 * m->Jd[e * Np + a]);
+                }
+            } else {
+                for (int r = 0; r < 3; ++r) s += (fabs(qa[1 + r] / qa[0]) + c) / m->h[r];
+            }
             if (s > smax) smax = s;
         }
     return cfl / ((m->N + 1) * smax);
