@@ -75,7 +75,18 @@ typedef struct esdg_mesh *esdg_mesh_t;
  *   precision    ESDG_FP64 or ESDG_FP32_MIXED
  *   ref_rho/ref_p  FP32_MIXED only: device arrays [e][n] (FP64) holding the
  *                hydrostatic reference state; NULL for FP64
- *   epw          elements per workgroup; 0 = the library's choice */
+ *   epw          elements per workgroup; 0 = the library's choice
+ *   curved       0: the affine box.  1: curved hexahedra (paper Sec. 3,
+ *                metric terms G): the box warped by
+ *                X_d = x_d + warp[d] L_d prod_c sin(2 pi k_dc s_c),
+ *                s = (x - lo)/L, k_dc = 2 for c = d > 0 and 1 otherwise,
+ *                which vanishes on the box faces (planar walls, matching
+ *                periodic faces).  Metric terms in the conservative curl
+ *                form, built on the host at creation (88 B per node of
+ *                device geometry plus 24 B of coordinates).  FP64 only,
+ *                Rusanov or EC faces, not packable; a warp that folds an
+ *                element (J <= 0) is rejected (ESDG_EINVAL).
+ *   warp[3]      the warp amplitudes (fractions of the box lengths) */
 typedef struct {
     int32_t N;
     int32_t K[3];
@@ -91,6 +102,8 @@ typedef struct {
     const double *ref_rho;
     const double *ref_p;
     int32_t epw;
+    int32_t curved;
+    double warp[3];
 } esdg_mesh_desc;
 
 /* Create a mesh bound to `hip_stream` (a hipStream_t; NULL = the default

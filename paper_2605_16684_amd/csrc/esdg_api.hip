@@ -13,10 +13,12 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "esdg.h"
 #include "esdg_device.hpp"
 #include "esdg_mixed.hpp"
+#include "esdg_curved.hpp"
 
 using namespace esdg;
 
@@ -193,6 +195,12 @@ struct esdg_mesh {
     float *d_ref_r;      // FP32_MIXED: reference density (FP32 values)
     float *d_ref_p;      // FP32_MIXED: reference pressure
     float *d_rr_mom;     // FP32_MIXED: momentum components of R(q_r)
+    bool curved;         // curved hexahedra: per-node metric terms below
+    double *d_Ja;        // [e][r][d][n] J a^r_d
+    double *d_iJ;        // [e][n] 1/J
+    double *d_J;         // [e][n] J
+    double *d_phi;       // [e][n] geopotential
+    double *d_xyz;       // [e][3][n] node coordinates
     int64_t red_blocks;
     int64_t footprint;
     // captured two-step graph for esdg_lsrk_run
@@ -249,6 +257,28 @@ const MixedVariant kMixedVariants[] = {
     VM(5, 3), VM(6, 2), VM(7, 1), VM(7, 2), VM(8, 1),
 };
 #undef VM
+
+typedef void (*curved_kernel_t)(CurvedParams);
+
+struct CurvedVariant {
+    int N, epw, threads;
+    curved_kernel_t rhs, stage;
+};
+
+#define VC(NN, E)                                                                            \
+    {NN, E, block_threads<NN + 1, E>(), stage_curved<NN + 1, E, MODE_RHS>,                  \
+     stage_curved<NN + 1, E, MODE_STAGE>}
+const CurvedVariant kCurvedVariants[] = {
+    VC(1, 16), VC(2, 7), VC(3, 4), VC(4, 5), VC(5, 3), VC(6, 1), VC(7, 1), VC(8, 1),
+};
+#undef VC
+
+const CurvedVariant *find_curved_variant(int N, int epw)
+{
+    for (const CurvedVariant &v : kCurvedVariants)
+        if (v.N == N && v.epw == epw) return &v;
+    return nullptr;
+}
 
 const Variant *find_variant(int N, int epw)
 {
@@ -314,6 +344,9 @@ GeomParams geom(const esdg_mesh *m)
     G.gamma = m->desc.gamma;
     G.grav = m->desc.grav;
     G.lnz_scale = m->desc.gas_R * 300.0;
+    G.Jn = m->curved ? m->d_J : nullptr;
+    G.Ja = m->curved ? m->d_Ja : nullptr;
+    G.phi = m->curved ? m->d_phi : nullptr;
     return G;
 }
 
@@ -365,8 +398,27 @@ int launch_stage_fp64(esdg_mesh *m, StageParams P, int epw)
     return ESDG_OK;
 }
 
+int launch_stage_curved(esdg_mesh *m, StageParams P)
+{
+    const CurvedVariant *v = find_curved_variant(m->N, m->epw);
+    if (!v) return fail(ESDG_EINVAL, "no curved kernel variant for N=%d epw=%d", m->N, m->epw);
+    const int64_t nb = (m->ne + m->epw - 1) / m->epw;
+    if (nb > 0x7fffffff) return fail(ESDG_EINVAL, "mesh too large");
+    P.nblocks = (int)nb;
+    CurvedParams C;
+    C.s = P;
+    C.Ja = m->d_Ja;
+    C.iJ = m->d_iJ;
+    C.phi = m->d_phi;
+    hipLaunchKernelGGL(P.mode == MODE_RHS ? v->rhs : v->stage, dim3((unsigned)nb),
+                       dim3(v->threads), 0, m->stream, C);
+    HIP_TRY(hipGetLastError());
+    return ESDG_OK;
+}
+
 int launch_stage(esdg_mesh *m, StageParams P)
 {
+    if (m->curved) return launch_stage_curved(m, P);
     if (m->desc.precision != ESDG_FP32_MIXED) return launch_stage_fp64(m, P, m->epw);
     const MixedVariant *v = find_mixed_variant(m->N, m->epw);
     if (!v) return fail(ESDG_EINVAL, "no mixed kernel variant for N=%d epw=%d", m->N, m->epw);
@@ -461,6 +513,104 @@ void release_scratch(esdg_mesh *m, double **buf)
     (void)hipFree(*buf);
     *buf = nullptr;
     m->footprint -= (int64_t)(sizeof(double) * (size_t)m->state_len);
+}
+
+// sin(2 pi k s), exactly 0 at s = 0 and s = 1 (the box faces).
+double sin2pik(int k, double s)
+{
+    if (s == 0.0 || s == 1.0) return 0.0;
+    return std::sin(2.0 * 3.14159265358979323846 * k * s);
+}
+
+// Curved set-up (host, once per mesh): node coordinates of the warped box
+//   X_d = x_d + warp_d L_d prod_c sin(2 pi k_dc s_c),  s = (x - lo)/L,
+//   k_dc = 2 for c = d > 0, else 1,
+// which vanishes on the box faces; the metric terms J a^r_d in the
+// conservative curl form J a^i_n = -e_i . curl_xi(X_l grad_xi X_m) ((n, m, l)
+// cyclic), which satisfies the discrete metric identities; J = det(dX/dxi);
+// phi = g z.  Derivatives are the library's LGL derivative matrix applied
+// along one reference direction.
+int setup_curved(esdg_mesh *m)
+{
+    const int N = m->N, Nq = m->Nq, Np = m->Np;
+    const esdg_mesh_desc &d = m->desc;
+    std::vector<double> xi(Nq), wts(Nq), Dm(Nq * Nq);
+    lgl_tables(N, xi.data(), wts.data(), Dm.data());
+    const size_t nn = (size_t)m->nn;
+    std::vector<double> xyz(3 * nn), Ja(9 * nn), iJ(nn), Jd(nn), phi(nn);
+    double L[3];
+    for (int c = 0; c < 3; ++c) L[c] = d.hi[c] - d.lo[c];
+    std::vector<double> X(3 * Np), dX(9 * Np), Y(3 * Np);
+    auto deriv = [&](const double *f, int n, int j) {
+        int ii[3] = {n % Nq, (n / Nq) % Nq, n / (Nq * Nq)};
+        const int row = ii[j];
+        double acc = 0.0;
+        for (int l = 0; l < Nq; ++l) {
+            ii[j] = l;
+            acc += Dm[row * Nq + l] * f[ii[0] + Nq * (ii[1] + Nq * ii[2])];
+        }
+        return acc;
+    };
+    for (int64_t e = 0; e < m->ne; ++e) {
+        const int ec[3] = {(int)(e % d.K[0]), (int)((e / d.K[0]) % d.K[1]),
+                           (int)(e / ((int64_t)d.K[0] * d.K[1]))};
+        for (int n = 0; n < Np; ++n) {
+            const int ii[3] = {n % Nq, (n / Nq) % Nq, n / (Nq * Nq)};
+            double xh[3], sv[3];
+            for (int c = 0; c < 3; ++c) {
+                const double XL = d.lo[c] + (d.hi[c] - d.lo[c]) * ((double)ec[c] / (double)d.K[c]);
+                const double XR =
+                    d.lo[c] + (d.hi[c] - d.lo[c]) * ((double)(ec[c] + 1) / (double)d.K[c]);
+                const double t = xi[ii[c]];
+                xh[c] = 0.5 * (1.0 - t) * XL + 0.5 * (1.0 + t) * XR;
+                sv[c] = (xh[c] - d.lo[c]) / L[c];
+            }
+            for (int c = 0; c < 3; ++c) {
+                double sn = 1.0;
+                for (int b = 0; b < 3; ++b) sn *= sin2pik((b == c && c > 0) ? 2 : 1, sv[b]);
+                X[c * Np + n] = xh[c] + d.warp[c] * L[c] * sn;
+            }
+        }
+        for (int c = 0; c < 3; ++c)
+            for (int j = 0; j < 3; ++j)
+                for (int n = 0; n < Np; ++n) dX[(c * 3 + j) * Np + n] = deriv(&X[c * Np], n, j);
+        const size_t eo = (size_t)e * Np;
+        for (int n = 0; n < Np; ++n) {
+            auto a = [&](int c, int j) { return dX[(c * 3 + j) * Np + n]; };
+            const double J = a(0, 0) * (a(1, 1) * a(2, 2) - a(1, 2) * a(2, 1)) -
+                             a(0, 1) * (a(1, 0) * a(2, 2) - a(1, 2) * a(2, 0)) +
+                             a(0, 2) * (a(1, 0) * a(2, 1) - a(1, 1) * a(2, 0));
+            if (!(J > 0.0)) return fail(ESDG_EINVAL, "warp folds element %lld (J <= 0)", (long long)e);
+            Jd[eo + n] = J;
+            iJ[eo + n] = 1.0 / J;
+            for (int c = 0; c < 3; ++c) xyz[((size_t)e * 3 + c) * Np + n] = X[c * Np + n];
+            phi[eo + n] = d.grav * X[2 * Np + n];
+        }
+        for (int nc = 0; nc < 3; ++nc) {
+            const int mc = (nc + 1) % 3, lc = (nc + 2) % 3;
+            for (int j = 0; j < 3; ++j)
+                for (int n = 0; n < Np; ++n) Y[j * Np + n] = X[lc * Np + n] * dX[(mc * 3 + j) * Np + n];
+            for (int i = 0; i < 3; ++i) {
+                const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+                for (int n = 0; n < Np; ++n)
+                    Ja[(((size_t)e * 3 + i) * 3 + nc) * Np + n] =
+                        deriv(&Y[i1 * Np], n, i2) - deriv(&Y[i2 * Np], n, i1);
+            }
+        }
+    }
+    struct Buf {
+        double **dst;
+        const std::vector<double> *src;
+    } bufs[] = {{&m->d_Ja, &Ja}, {&m->d_iJ, &iJ}, {&m->d_J, &Jd}, {&m->d_phi, &phi},
+                {&m->d_xyz, &xyz}};
+    for (const Buf &b : bufs) {
+        const size_t bytes = sizeof(double) * b.src->size();
+        if (hipMalloc(b.dst, bytes) != hipSuccess)
+            return fail(ESDG_ENOMEM, "curved geometry (%.1f MB)", bytes / 1e6);
+        m->footprint += (int64_t)bytes;
+        HIP_TRY(hipMemcpy(*b.dst, b.src->data(), bytes, hipMemcpyHostToDevice));
+    }
+    return ESDG_OK;
 }
 
 // FP32_MIXED set-up: round the caller's reference to FP32, build the FP64
@@ -568,8 +718,17 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         if ((rc0 = check_ptr(d->ref_rho, "ref_rho")) || (rc0 = check_ptr(d->ref_p, "ref_p")))
             return rc0;
     }
+    if (d->curved != 0 && d->curved != 1) return fail(ESDG_EINVAL, "curved must be 0 or 1");
+    if (d->curved) {
+        if (d->precision != ESDG_FP64)
+            return fail(ESDG_EINVAL, "curved meshes run in FP64 only");
+        if (d->surface_flux == ESDG_SURF_MATRIX)
+            return fail(ESDG_EINVAL, "matrix dissipation on curved meshes is not built");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(d->warp[k])) return fail(ESDG_EINVAL, "warp[%d] is not finite", k);
+    }
     const int epw = d->epw ? d->epw : default_epw(d->N, d->precision);
-    if (!has_variant(d->precision, d->N, epw))
+    if (d->curved ? !find_curved_variant(d->N, epw) : !has_variant(d->precision, d->N, epw))
         return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", d->N, epw);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -607,6 +766,15 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         esdg_mesh_destroy(m);
         return fail(ESDG_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e8));
     }
+    m->curved = d->curved != 0;
+    if (m->curved) {
+        rc = setup_curved(m);
+        if (rc) {
+            const std::string msg = g_err;
+            esdg_mesh_destroy(m);
+            return fail(rc, "%s", msg.c_str());
+        }
+    }
     if (d->precision == ESDG_FP32_MIXED) {
         rc = setup_reference(m);
         if (rc) {
@@ -636,6 +804,8 @@ int esdg_mesh_destroy(esdg_mesh_t m)
     if (m->d_ref_r) (void)hipFree(m->d_ref_r);
     if (m->d_ref_p) (void)hipFree(m->d_ref_p);
     if (m->d_rr_mom) (void)hipFree(m->d_rr_mom);
+    for (double *b : {m->d_Ja, m->d_iJ, m->d_J, m->d_phi, m->d_xyz})
+        if (b) (void)hipFree(b);
     if (m->h_out) (void)hipHostFree(m->h_out);
     if (m->h_flag) (void)hipHostFree(m->h_flag);
     delete m;
@@ -667,7 +837,7 @@ int esdg_set_epw(esdg_mesh_t m, int32_t epw)
     int rc = check_mesh(m);
     if (rc) return rc;
     const int e = epw ? epw : default_epw(m->N, m->desc.precision);
-    if (!has_variant(m->desc.precision, m->N, e))
+    if (m->curved ? !find_curved_variant(m->N, e) : !has_variant(m->desc.precision, m->N, e))
         return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", m->N, e);
     m->epw = e;
     drop_graph(m);
@@ -687,6 +857,11 @@ int esdg_node_coords(esdg_mesh_t m, double *xyz)
 {
     int rc = check_mesh(m);
     if (rc || (rc = check_ptr(xyz, "xyz")) || (rc = set_device(m))) return rc;
+    if (m->curved) {
+        HIP_TRY(hipMemcpyAsync(xyz, m->d_xyz, sizeof(double) * 3 * (size_t)m->nn,
+                               hipMemcpyDeviceToDevice, m->stream));
+        return ESDG_OK;
+    }
     GeomParams G = geom(m);
     const int64_t n = m->nn;
     hipLaunchKernelGGL(node_coords_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
@@ -981,6 +1156,7 @@ int esdg_pack_set_members(esdg_pack_t p, int32_t n, const esdg_mesh_t *meshes, d
         if (!m) return fail(ESDG_EINVAL, "member %d: NULL mesh", i);
         if (m->N != N || m->desc.precision != prec || m->epw != epw || m->device != p->device)
             return fail(ESDG_EINVAL, "member %d: N, precision, epw and device must match", i);
+        if (m->curved) return fail(ESDG_EINVAL, "member %d: curved meshes are not packed", i);
         int rc;
         if ((rc = check_ptr(q0[i], "q0")) || (rc = check_ptr(q1[i], "q1")) ||
             (rc = check_ptr(dq[i], "dq")))

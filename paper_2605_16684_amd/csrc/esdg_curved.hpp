@@ -1,0 +1,311 @@
+// esdg_curved.hpp -- fused ES-DGSEM stage kernel on curved hexahedra.
+//
+// The affine kernel's metric factors 2/h_r become per-node metric terms
+// (Sec. 3: the metric terms G and the Jacobian of the semi-discrete form).
+// With J a^r the contravariant basis vector of direction r times the
+// Jacobian J:
+//   volume:  R_a += -(1/J_a) sum_r (1/w_i) sum_b S_ab sum_d {{J a^r_d}}_ab F_d(a, b),
+//            where F_d is the two-point flux of direction d, whose momentum
+//            part carries the pressure and the gravity term G_ab = rho_hat
+//            [[phi]]/2 in component d; the sum over d is taken in closed form
+//            (the flux along the averaged vector n = {{J a^r}});
+//   faces:   R_a += -(1/(J_a w_0)) F*(q-, q+; s J a^r(a)), the face flux
+//            along the unnormalised outward normal s J a^r, with the Rusanov
+//            speed of the unit normal scaled by |J a^r|.
+// The geopotential varies along every line of a curved element, so the
+// gravity term appears in all three directions.  The line-per-lane layout,
+// the LDS accumulator of the affine kernel and the face handling are kept;
+// the metric terms, 1/J and phi are read per node from HBM (88 B per node
+// per stage beyond the state).
+#pragma once
+
+#include "esdg_device.hpp"
+
+namespace esdg {
+
+struct CurvedParams {
+    StageParams s;
+    const double *Ja;   // [e][r][d][n]  J a^r_d
+    const double *iJ;   // [e][n]        1/J
+    const double *phi;  // [e][n]        geopotential
+};
+
+// Symmetric two-point flux along the vector n (the averaged J a^r of a pair,
+// or a face normal): f^rho = {{rho}}_log (n.{{u}}),
+// f^m = f^rho {{u}} + n {{p}},
+// f^E = f^rho (1/((gamma-1) {{rho/p}}_log) + u_a.u_b/2 + phi_m)
+//       + (p_a (n.u_b) + p_b (n.u_a))/2.   Returns {{rho}}_log.
+__device__ __forceinline__ double sym_flux_vec(const Node &a, const Node &b, double rho_ln,
+                                               double izln, const double n[3], double phi_m,
+                                               double gm1i, double S[5])
+{
+    const double una = n[0] * a.h0 + n[1] * a.h1 + n[2] * a.h2;  // (n.u_a)/2
+    const double unb = n[0] * b.h0 + n[1] * b.h1 + n[2] * b.h2;
+    const double frho = rho_ln * (una + unb);
+    const double pm = a.hp + b.hp;  // {{p}}
+    S[0] = frho;
+    S[1] = frho * (a.h0 + b.h0) + n[0] * pm;
+    S[2] = frho * (a.h1 + b.h1) + n[1] * pm;
+    S[3] = frho * (a.h2 + b.h2) + n[2] * pm;
+    const double hh = a.h0 * b.h0 + a.h1 * b.h1 + a.h2 * b.h2;
+    const double cross = a.hp * unb + b.hp * una;
+    S[4] = frho * (izln * gm1i + 2.0 * hh + phi_m) + 2.0 * cross;
+    return rho_ln;
+}
+
+// Both log-means of a pair with the branch rule; logarithms taken here only
+// on the log branch.
+__device__ __forceinline__ void pair_log_means(const Node &a, const Node &b,
+                                               const StageParams &P, double &rho_ln,
+                                               double &izln)
+{
+    {
+        const double d = b.r - a.r, sm = a.r + b.r;
+        const bool ser = fabs(d) < LM_SQRT_EPS * sm;
+        double den = sm;
+        if (!ser) den = log(b.r) - log(a.r);
+        const double x = fdiv(d, den);
+        const double u = x * x;
+        rho_ln = ser ? 0.5 * sm * (1.0 - u * (S1 + u * (S2 + u * S3))) : x;
+    }
+    {
+        const double d = b.z - a.z, sm = a.z + b.z;
+        const bool ser = fabs(d) < LM_SQRT_EPS * sm;
+        double num = 1.0, den = sm;
+        if (!ser) {
+            num = log(b.z * P.lnz_scale) - log(a.z * P.lnz_scale);
+            den = d;
+        }
+        const double x = fdiv(num, den);
+        const double dx = d * x;
+        const double u = dx * dx;
+        izln = ser ? 2.0 * x * (1.0 + u * (I1 + u * (I2 + u * I3))) : x;
+    }
+}
+
+// Face flux along the unnormalised outward normal Nv = s J a^r at a face
+// node (phi on both sides): the EC flux along Nv minus the Rusanov term
+// |Nv| lambda/2 (q+ - q-), lambda = max(|u.n| + c) with n = Nv/|Nv|.
+__device__ __forceinline__ void face_flux_vec(const Node &a, const Cons &qm, const Cons &qp,
+                                              double phi, const double Nv[3],
+                                              const StageParams &P, double Fn[5])
+{
+    const double g = P.gamma, gm1 = g - 1.0;
+    const Node b = primitives(qp, phi, gm1);
+    double rho_ln, izln;
+    pair_log_means(a, b, P, rho_ln, izln);
+    double S[5];
+    sym_flux_vec(a, b, rho_ln, izln, Nv, phi, P.gm1i, S);
+    double hl = 0.0;
+    if (P.surf == SURF_RUSANOV) {
+        const double n2 = Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2];
+        const double nrm = sqrt_pos(n2);
+        const double una = 2.0 * fabs(Nv[0] * a.h0 + Nv[1] * a.h1 + Nv[2] * a.h2);
+        const double unb = 2.0 * fabs(Nv[0] * b.h0 + Nv[1] * b.h1 + Nv[2] * b.h2);
+        // |u.Nv| + c |Nv| = |Nv| (|u.n| + c)
+        const double la = una + sqrt_pos(g * a.zi) * nrm;
+        const double lb = unb + sqrt_pos(g * b.zi) * nrm;
+        hl = 0.5 * (la > lb ? la : lb);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fn[v] = S[v] - hl * (qp.v[v] - qm.v[v]);
+}
+
+// Volume and face sums of one R-line of a curved element (without the 1/J
+// of the finish).  KEEP copies the line's conservative states to qkeep.
+template <int NQ, int R, bool KEEP = false>
+__device__ __forceinline__ void line_terms_curved(const CurvedParams &C, const OrderTables &tb,
+                                                  int m, int64_t e, const int ec[3],
+                                                  double acc[NQ][5],
+                                                  double (*qkeep)[5] = nullptr)
+{
+    constexpr int NQ3 = NQ * NQ * NQ;
+    const StageParams &P = C.s;
+    const double gm1 = P.gamma - 1.0;
+#pragma unroll
+    for (int a = 0; a < NQ; ++a)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[a][v] = 0.0;
+
+    Cons qc[NQ];
+    double ph[NQ], jr[NQ][3];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+        const int n = line_node<NQ, R>(m, t);
+        load_cons(P.q_in, e, NQ3, n, qc[t]);
+        ph[t] = C.phi[e * NQ3 + n];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) jr[t][d] = C.Ja[((e * 3 + R) * 3 + d) * NQ3 + n];
+    }
+    const bool faces = (P.mask & TERM_FACE) != 0;
+    Cons qp[2];
+    if (faces) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+            plus_state<NQ, R>(P, m, ec, side, qc[side ? NQ - 1 : 0], qp[side]);
+    }
+    if (KEEP) {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qkeep[t][v] = qc[t].v[v];
+    }
+    Node nd[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) nd[t] = primitives(qc[t], ph[t], gm1);
+
+    if (faces) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int t = side ? NQ - 1 : 0;
+            const double s = side ? 1.0 : -1.0;
+            const double Nv[3] = {s * jr[t][0], s * jr[t][1], s * jr[t][2]};
+            double Fn[5];
+            face_flux_vec(nd[t], qc[t], qp[side], ph[t], Nv, P, Fn);
+            const double wi = tb.winv[t];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[t][v] -= wi * Fn[v];
+        }
+    }
+
+    if (P.mask & TERM_VOL) {
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+#pragma unroll
+            for (int b = a + 1; b < NQ; ++b) {
+                const double n[3] = {0.5 * (jr[a][0] + jr[b][0]), 0.5 * (jr[a][1] + jr[b][1]),
+                                     0.5 * (jr[a][2] + jr[b][2])};
+                double rho_ln, izln, S[5];
+                pair_log_means(nd[a], nd[b], P, rho_ln, izln);
+                sym_flux_vec(nd[a], nd[b], rho_ln, izln, n, 0.5 * (ph[a] + ph[b]), P.gm1i, S);
+                const double tab = tb.T[a][b], tba = tb.T[b][a];
+                // gravity G_ab = rho_hat [[phi]]/2 along n, rho_hat = {{b}} {{rho}}_log / b_a;
+                // partner G_ba = -G_ab z_a / z_b
+                const double X = 0.25 * rho_ln * (nd[a].z + nd[b].z) * (ph[b] - ph[a]);
+                const double ga = X * nd[a].zi, gb = X * nd[b].zi;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    acc[a][v] -= tab * S[v];
+                    acc[b][v] -= tba * S[v];
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    acc[a][1 + d] -= tab * (n[d] * ga);
+                    acc[b][1 + d] += tba * (n[d] * gb);
+                }
+            }
+        }
+    }
+}
+
+template <int NQ, int EPW, int MODE>
+__device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
+{
+    constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
+    __shared__ double sacc[5][EPW][NQ3];
+    const StageParams &P = C.s;
+    const OrderTables &tb = c_tab[NQ - 2];
+    const int tid = threadIdx.x;
+    const int el = tid / NQ2;
+    const int m = tid - el * NQ2;
+    const int64_t it = (int64_t)lb * EPW + el;
+    const bool act = (el < EPW) && (it < P.ne);
+    int ec[3] = {0, 0, 0};
+    int64_t e = 0;
+    if (act) e = tile_element(P, it, ec);
+    double acc[NQ][5];
+    const bool vol_or_face = (P.mask & (TERM_VOL | TERM_FACE)) != 0;
+    const int64_t base0 = e * 5 * NQ3 + m;
+
+    // x phase
+    if (act) {
+        if (vol_or_face) {
+            line_terms_curved<NQ, 0>(C, tb, m, e, ec, acc);
+        } else {
+#pragma unroll
+            for (int t = 0; t < NQ; ++t)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[t][v] = 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const int n = line_node<NQ, 0>(m, t);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sacc[v][el][n] = acc[t][v];
+        }
+    }
+    __syncthreads();
+    // y phase
+    if (act && vol_or_face) {
+        line_terms_curved<NQ, 1>(C, tb, m, e, ec, acc);
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            const int n = line_node<NQ, 1>(m, t);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) sacc[v][el][n] += acc[t][v];
+        }
+    }
+    __syncthreads();
+    // z phase and finish
+    if (!act) return;
+    const bool src = (P.mask & TERM_SRC) != 0;
+    double qv[NQ][5];
+    if (vol_or_face) {
+        line_terms_curved<NQ, 2, true>(C, tb, m, e, ec, acc, qv);
+    } else {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                acc[t][v] = 0.0;
+                qv[t][v] = P.q_in[base0 + v * NQ3 + NQ2 * t];
+            }
+    }
+    const bool use_dq = P.A != 0.0;
+    double dv[NQ][5];
+    if (MODE == MODE_STAGE && use_dq) {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) dv[t][v] = P.dq[base0 + v * NQ3 + NQ2 * t];
+    }
+    bool bad = false;
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+        const int n = m + NQ2 * t;
+        const double iJ = C.iJ[e * NQ3 + n];
+        double Rv[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Rv[v] = (sacc[v][el][n] + acc[t][v]) * iJ;
+        if (src) {
+            Rv[1] += P.cor_f * qv[t][2];
+            Rv[2] -= P.cor_f * qv[t][1];
+        }
+        if (MODE == MODE_RHS) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) store_f64<true>(&P.r_out[base0 + v * NQ3 + NQ2 * t], Rv[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double d = use_dq ? P.A * dv[t][v] + P.dt * Rv[v] : P.dt * Rv[v];
+                P.dq[base0 + v * NQ3 + NQ2 * t] = d;
+                P.q_out[base0 + v * NQ3 + NQ2 * t] = qv[t][v] + P.B * d;
+            }
+        }
+        if (P.flag) {
+            const double r = qv[t][0];
+            const double kin = qv[t][1] * qv[t][1] + qv[t][2] * qv[t][2] + qv[t][3] * qv[t][3];
+            const double eint = qv[t][4] - 0.5 * kin / r - r * C.phi[e * NQ3 + n];
+            bad |= !(r > 0.0) || !(eint > 0.0);
+        }
+    }
+    if (bad) atomicOr(P.flag, 1);
+}
+
+template <int NQ, int EPW, int MODE>
+__global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_curved(const CurvedParams C)
+{
+    stage_curved_body<NQ, EPW, MODE>(C, xcd_remap(blockIdx.x, C.s.nblocks));
+}
+
+}  // namespace esdg

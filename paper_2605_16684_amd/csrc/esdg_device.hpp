@@ -856,6 +856,10 @@ struct GeomParams {
     double lo[3], hi[3];
     double h[3];
     double gamma, grav, lnz_scale;
+    // curved meshes (NULL on the affine box): per-node J, J a^r_d, phi
+    const double *Jn;
+    const double *Ja;
+    const double *phi;
 };
 
 __device__ __forceinline__ double vertex(const GeomParams &G, int d, int e)
@@ -902,8 +906,9 @@ __global__ void __launch_bounds__(RED_THREADS)
         const int ez = (int)(e / ((int64_t)G.K[0] * G.K[1]));
         const double s = tb.xi[k];
         const double ZL = vertex(G, 2, ez), ZR = vertex(G, 2, ez + 1);
-        const double phi = G.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
-        const double J = G.h[0] * G.h[1] * G.h[2] * 0.125;
+        const double phi = G.phi ? G.phi[e * NP + n]
+                                 : G.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
+        const double J = G.Jn ? G.Jn[e * NP + n] : G.h[0] * G.h[1] * G.h[2] * 0.125;
         const double wq = J * tb.w[i] * tb.w[j] * tb.w[k];
         const int64_t base = e * 5 * NP + n;
         const double rho = q[base], m0 = q[base + NP], m1 = q[base + 2 * NP],
@@ -973,7 +978,8 @@ __global__ void __launch_bounds__(RED_THREADS)
         const int ez = (int)(e / ((int64_t)G.K[0] * G.K[1]));
         const double s = tb.xi[k];
         const double ZL = vertex(G, 2, ez), ZR = vertex(G, 2, ez + 1);
-        const double phi = G.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
+        const double phi = G.phi ? G.phi[e * NP + n]
+                                 : G.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
         const int64_t base = e * 5 * NP + n;
         const double rho = q[base];
         const double u[3] = {q[base + NP] / rho, q[base + 2 * NP] / rho, q[base + 3 * NP] / rho};
@@ -981,7 +987,22 @@ __global__ void __launch_bounds__(RED_THREADS)
                          (q[base + 4 * NP] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
                           rho * phi);
         const double c = sqrt(G.gamma * p / rho);
-        smax = (fabs(u[0]) + c) / G.h[0] + (fabs(u[1]) + c) / G.h[1] + (fabs(u[2]) + c) / G.h[2];
+        if (G.Ja) {
+            // (|u . J a^r| + c |J a^r|) / (2 J): on the affine box (|u_r| + c) / h_r
+            smax = 0.0;
+            for (int r = 0; r < 3; ++r) {
+                double un = 0.0, n2 = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    const double jv = G.Ja[((e * 3 + r) * 3 + d) * NP + n];
+                    un += u[d] * jv;
+                    n2 += jv * jv;
+                }
+                smax += (fabs(un) + c * sqrt(n2)) / (2.0 * G.Jn[e * NP + n]);
+            }
+        } else {
+            smax = (fabs(u[0]) + c) / G.h[0] + (fabs(u[1]) + c) / G.h[1] +
+                   (fabs(u[2]) + c) / G.h[2];
+        }
         if (!(smax == smax)) smax = INFINITY;
     }
     sh[threadIdx.x] = smax;

@@ -48,6 +48,8 @@ class MeshDesc(C.Structure):
         ("ref_rho", C.c_void_p),
         ("ref_p", C.c_void_p),
         ("epw", C.c_int32),
+        ("curved", C.c_int32),
+        ("warp", C.c_double * 3),
     ]
 
 
@@ -165,6 +167,9 @@ class Mesh:
         d.ref_rho = ref_rho.data_ptr() if ref_rho is not None else None
         d.ref_p = ref_p.data_ptr() if ref_p is not None else None
         d.epw = epw
+        warp = getattr(spec, "warp", None)
+        d.curved = 0 if warp is None else 1
+        d.warp[:] = [0.0, 0.0, 0.0] if warp is None else [float(x) for x in warp]
         self._desc = d
         h = C.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream

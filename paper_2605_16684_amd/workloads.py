@@ -53,6 +53,9 @@ class MeshSpec:
     grav: float = GRAV
     coriolis_f: float = 0.0
     surface_flux: int = 0  # 0 Rusanov, 1 entropy-conservative, 2 matrix dissipation
+    # curved hexahedra: warp amplitudes (fractions of the box lengths) of the
+    # displacement that vanishes on the box faces; None = the affine box
+    warp: Optional[Tuple[float, float, float]] = None
 
     @property
     def n_elem(self) -> int:

@@ -1,0 +1,160 @@
+"""Curved hexahedra on the HIP path (the box warped by a displacement that
+vanishes on its faces; Sec. 3 metric terms): parity with the curved oracle
+to the FP64 bars, agreement of the curved code path with the affine one at
+zero warp, and the properties the metric terms must keep (free stream,
+isothermal balance, entropy conservation with EC faces)."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_16684_amd import workloads as W
+from tests._parity import TOL_RHS, TOL_STATE, err_gross, err_net, kappa
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+WARP = (0.05, 0.04, 0.03)
+
+
+def _esdg():
+    from paper_2605_16684_amd import esdg
+    return esdg
+
+
+def _oracle_mesh(spec):
+    return O.Mesh(spec.N, spec.K, spec.lo, spec.hi, spec.periodic, gamma=spec.gamma,
+                  gas_R=spec.gas_R, grav=spec.grav, coriolis_f=spec.coriolis_f,
+                  surface_flux=spec.surface_flux, warp=spec.warp)
+
+
+def _with_jumps(q, seed):
+    rng = np.random.default_rng(seed)
+    q = q.copy()
+    q *= (1.0 + 0.02 * rng.uniform(-1, 1, size=q[:, 0].shape))[:, None, :]
+    q[:, 1:4] += 5.0 * q[:, 0:1] * rng.uniform(-1, 1, size=q[:, 1:4].shape)
+    return q
+
+
+_BOX = ((0, 0, 0), (900.0, 700.0, 1100.0))
+CASES = [
+    # name, N, K, periodic, coriolis_f, surface flux, state
+    ("N1_walls", 1, (3, 2, 2), (0, 0, 0), 0.0, 0, "iso_pert"),
+    ("N2_mixed", 2, (2, 3, 2), (1, 0, 0), 1e-4, 0, "jumps"),
+    ("N3_ragged", 3, (3, 3, 2), (0, 1, 0), 0.0, 0, "jumps"),
+    ("N4_periodic_xy", 4, (3, 2, 2), (1, 1, 0), 1e-4, 0, "jumps"),
+    ("N4_ec", 4, (2, 2, 3), (1, 1, 0), 0.0, 1, "jumps"),
+    ("N5", 5, (2, 2, 2), (1, 0, 0), 0.0, 0, "iso_pert"),
+    ("N6", 6, (1, 2, 2), (0, 1, 0), 0.0, 0, "jumps"),
+    ("N7", 7, (2, 1, 2), (1, 1, 0), 1e-4, 0, "jumps"),
+    ("N8", 8, (1, 1, 2), (0, 0, 0), 0.0, 0, "iso_pert"),
+]
+
+
+@pytest.mark.parametrize("name,N,K,periodic,f,surf,state", CASES, ids=[c[0] for c in CASES])
+def test_curved_rhs_parity(name, N, K, periodic, f, surf, state):
+    esdg = _esdg()
+    spec = W.MeshSpec(N, K, *_BOX, periodic, coriolis_f=f, surface_flux=surf, warp=WARP)
+    om = _oracle_mesh(spec)
+    q = W.state_iso_pert(om.coords(), spec, seed=6)
+    if state == "jumps":
+        q = _with_jumps(q, 6)
+    r_or, g = om.rhs(q, gross=True)
+    m = esdg.Mesh(spec)
+    r = m.rhs(torch.from_numpy(q).cuda()).cpu().numpy()
+    m.check()
+    eg, en, k = err_gross(r, r_or, g), err_net(r, r_or), kappa(r_or, g)
+    print(f"[curved {name}] err/gross={np.array2string(eg, precision=2)} "
+          f"err/net={np.array2string(en, precision=2)} kappa={np.array2string(k, precision=1)}",
+          flush=True)
+    assert np.all(eg <= TOL_RHS), eg
+
+
+def test_curved_node_coords_diagnostics_and_cfl_match_oracle():
+    esdg = _esdg()
+    spec = W.MeshSpec(3, (3, 2, 2), *_BOX, (1, 1, 0), warp=WARP)
+    om = _oracle_mesh(spec)
+    m = esdg.Mesh(spec)
+    x, xo = m.coords().cpu().numpy(), om.coords()
+    assert np.all(np.abs(x - xo) <= 1e-12 * np.abs(xo).max())
+    q = _with_jumps(W.state_iso_pert(xo, spec, seed=3), 3)
+    qg = torch.from_numpy(q).cuda()
+    eg, eo = m.entropy(qg), om.entropy(q)
+    for c in range(3):
+        assert abs(eg[c] - eo[c]) <= 1e-12 * abs(eo[c])
+    dt, dto = m.cfl_dt(qg, 0.5), om.cfl_dt(q, 0.5)
+    assert abs(dt - dto) <= 1e-12 * dto
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_zero_warp_curved_path_equals_affine_path(N):
+    esdg = _esdg()
+    spec = W.MeshSpec(N, (3, 2, 2), *_BOX, (1, 1, 0), coriolis_f=1e-4)
+    om = _oracle_mesh(spec)
+    q = _with_jumps(W.state_iso_pert(om.coords(), spec, seed=9), 9)
+    _, g = om.rhs(q, gross=True)
+    qg = torch.from_numpy(q).cuda()
+    ra = esdg.Mesh(spec).rhs(qg).cpu().numpy()
+    rc = esdg.Mesh(replace(spec, warp=(0.0, 0.0, 0.0))).rhs(qg).cpu().numpy()
+    eg = err_gross(rc, ra, g)
+    print(f"[zero warp N={N}] err/gross={np.array2string(eg, precision=2)}", flush=True)
+    assert np.all(eg <= 1e-14), eg
+
+
+def test_curved_lsrk_100_steps_parity():
+    esdg = _esdg()
+    spec = W.MeshSpec(3, (4, 4, 4), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 0), warp=WARP)
+    om = _oracle_mesh(spec)
+    q0 = W.state_iso_pert(om.coords(), spec, seed=1)
+    dt = om.cfl_dt(q0, 0.5)
+    q_or = om.run(q0, dt, 100)
+    m = esdg.Mesh(spec)
+    qg = torch.from_numpy(q0).cuda()
+    dq = torch.zeros_like(qg)
+    m.lsrk_run(qg, dq, dt, 100)
+    e = err_net(qg.cpu().numpy(), q_or)
+    print(f"[curved lsrk100] state rel L2 per var {np.array2string(e, precision=2)}", flush=True)
+    assert np.all(e <= TOL_STATE), e
+    # eager steps give the graph's bits
+    qe = torch.from_numpy(q0).cuda()
+    dqe = torch.zeros_like(qe)
+    for _ in range(100):
+        m.lsrk_step(qe, dqe, dt)
+    assert torch.equal(qe, qg)
+
+
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_curved_free_stream_balance_and_entropy(N):
+    esdg = _esdg()
+    # free stream without gravity, periodic
+    spec = W.MeshSpec(N, (3, 2, 2), *_BOX, (1, 1, 1), grav=0.0, warp=WARP)
+    om = _oracle_mesh(spec)
+    q = W.constant_state(om.ne, om.Np)
+    _, g = om.rhs(q, gross=True)
+    r = esdg.Mesh(spec).rhs(torch.from_numpy(q).cuda()).cpu().numpy()
+    assert np.all(err_gross(r, 0 * r, g) <= 1e-14), err_gross(r, 0 * r, g)
+    # isothermal atmosphere at rest
+    spec = W.MeshSpec(N, (2, 2, 4), (0, 0, 0), (2000.0, 2000.0, 30000.0), (1, 1, 0), warp=WARP)
+    om = _oracle_mesh(spec)
+    q = W.state_iso_rest(om.coords(), spec, T=250.0)
+    _, g = om.rhs(q, gross=True)
+    r = esdg.Mesh(spec).rhs(torch.from_numpy(q).cuda()).cpu().numpy()
+    assert np.all(err_gross(r, 0 * r, g) <= 1e-14), err_gross(r, 0 * r, g)
+    # entropy conservation with EC faces, periodic, no gravity, jumps everywhere
+    spec = W.MeshSpec(N, (2, 3, 2), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 1), grav=0.0,
+                      surface_flux=1, warp=WARP)
+    om = _oracle_mesh(spec)
+    q = _with_jumps(W.state_iso_pert(om.coords(), spec, seed=3, amp_rho=5e-2, amp_u=20.0), 3)
+    e_gpu = esdg.Mesh(spec).entropy(torch.from_numpy(q).cuda())[3]
+    e_ru = esdg.Mesh(replace(spec, surface_flux=0)).entropy(torch.from_numpy(q).cuda())[3]
+    print(f"[curved entropy N={N}] EC {e_gpu:.3e} Rusanov {e_ru:.3e}", flush=True)
+    assert e_ru < 0.0
+    assert abs(e_gpu) <= 1e-10 * abs(e_ru)
+
+
+def test_folding_warp_is_rejected():
+    esdg = _esdg()
+    spec = W.MeshSpec(4, (2, 2, 2), *_BOX, (1, 1, 0), warp=(0.6, 0.6, 0.6))
+    with pytest.raises(esdg.EsdgError, match="folds"):
+        esdg.Mesh(spec)
