@@ -222,6 +222,53 @@ def surface_block(esdg, torch, spec, q, dt, steps, epw, value, t_rhs):
             "rhs_only_launch_ms": t_r * 1e3, "rhs_only_vs_rusanov": t_rhs / t_r}
 
 
+CURVED_WARP = (0.05, 0.04, 0.03)
+
+
+def curved_block(esdg, W, torch, perfmodel, wl, steps, value):
+    """The same workload on the warped box (curved hexahedra, per-node
+    metric terms): whole LSRK(5,4) steps and RHS launches, with the curved
+    kernel's algorithmic bytes (state plus 88 B of geometry per node)."""
+    stream = torch.cuda.current_stream()
+    spec = replace(wl.mesh, warp=CURVED_WARP)
+    m = esdg.Mesh(spec)
+    q = W.make_state(wl.kind, m.coords().cpu().numpy(), spec, seed=1)
+    q = torch.from_numpy(q).cuda()
+    dq = torch.zeros_like(q)
+    dt = m.cfl_dt(q, wl.cfl)
+    m.lsrk_run(q, dq, dt, 2)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    m.lsrk_run(q, dq, dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    m.check()
+    r = torch.empty_like(q)
+    for _ in range(3):
+        m.rhs(q, r)
+    nr = 20
+    e0.record(stream)
+    for _ in range(nr):
+        m.rhs(q, r)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_r = e0.elapsed_time(e1) * 1e-3 / nr
+    nn, N, epw = m.n_nodes, spec.N, m.epw
+    t_launch = ms * 1e-3 / (5 * steps)
+    gbs = perfmodel.bytes_per_node_curved(N) * nn / t_launch / 1e9
+    v = nn * 5.0 * steps / (ms * 1e-3)
+    m.close()
+    return {"warp": list(CURVED_WARP), "kernel": f"stage_curved<{N + 1},{epw}>",
+            "steps": steps, "ms_per_step": ms / steps, "dof_rhs_per_s": v,
+            "vs_affine": v / value, "launch_ms": t_launch * 1e3,
+            "algorithmic_bytes_per_launch": perfmodel.bytes_per_node_curved(N) * nn,
+            "achieved_gbs": gbs, "hbm_frac": gbs / perfmodel.HBM_PEAK_GBS,
+            "rhs_only_launch_ms": t_r * 1e3}
+
+
 def sweep_block(esdg, W, torch, orders=(3, 4, 5, 7), sizes=(2, 4, 8, 12, 16, 24, 32, 40),
                 max_nodes=4.0e7, steps=6):
     """Throughput against mesh size per order: LSRK steps on rising-bubble
@@ -274,6 +321,8 @@ def main():
                     help="interface dissipation of the headline run")
     ap.add_argument("--no-matrix-leg", action="store_true",
                     help="skip the matrix-dissipation run beside a Rusanov headline")
+    ap.add_argument("--no-curved-leg", action="store_true",
+                    help="skip the run of the same workload on curved (warped) hexahedra")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure throughput against mesh size for N in 3, 4, 5, 7")
     ap.add_argument("--calib-copy", action="store_true",
@@ -421,6 +470,11 @@ def main():
                                               args.epw, value, t_rhs)
     del q
     torch.cuda.empty_cache()
+    if args.surface == "rusanov" and not args.no_curved_leg:
+        log("[bench] curved hexahedra ...")
+        out["curved"] = curved_block(esdg, W, torch, perfmodel, wl,
+                                     2 * max(1, min(K, 40) // 2), value)
+        torch.cuda.empty_cache()
     if not args.no_precision:
         log("[bench] FP64 vs FP32-mixed ...")
         out["precision"] = precision_block(esdg, W, torch, steps=args.precision_steps,

@@ -54,6 +54,16 @@ def bytes_per_node(N: int, stage: bool = True, word: int = 8) -> float:
     return own + 6.0 * 5 * word / Nq
 
 
+# Curved hexahedra: per node the metric terms J a^r_d (9 words), 1/J and phi
+# are read once per stage (each phase reads the three J a^r of its own
+# direction).
+CURVED_GEOM_WORDS = 11
+
+
+def bytes_per_node_curved(N: int, stage: bool = True, word: int = 8) -> float:
+    return bytes_per_node(N, stage, word) + CURVED_GEOM_WORDS * word
+
+
 def ridge_fp64() -> float:
     return FP64_VECTOR_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
 

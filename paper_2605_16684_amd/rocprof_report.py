@@ -87,7 +87,7 @@ def cmd_traffic(a):
              "|---|---:|---:|---:|---:|"]
     rec = {}
     for name in sorted(fetch):
-        if "stage_fp" not in name or name not in write:
+        if "stage_" not in name or name not in write:
             continue
         fv, wv = fetch[name], write[name]
         n = min(len(fv), len(wv))
