@@ -83,6 +83,50 @@ __device__ __forceinline__ void pair_log_means(const Node &a, const Node &b,
     }
 }
 
+// Both log-means of a pair whose line stays inside the series range of both
+// (the caller has checked the whole line): no branch, no logarithm.
+__device__ __forceinline__ void pair_log_means_series(const Node &a, const Node &b,
+                                                      double &rho_ln, double &izln)
+{
+    const double dr = b.r - a.r, sr = a.r + b.r;
+    const double xr = dr * frcp(sr);
+    const double ur = xr * xr;
+    rho_ln = sr * (0.5 - ur * (H1 + ur * (H2 + ur * H3)));
+    const double dz = b.z - a.z, sz = a.z + b.z;
+    const double rz = frcp(sz);
+    const double fz = dz * rz;
+    const double uz = fz * fz;
+    izln = (rz + rz) * (1.0 + uz * (I1 + uz * (I2 + uz * I3)));
+}
+
+// Shares of one pair (a, b) of a line: the flux along the averaged J a^r and
+// the gravity term along it (partner G_ba = -G_ab z_a / z_b).
+template <int NQ>
+__device__ __forceinline__ void curved_pair_shares(const OrderTables &tb, const Node nd[NQ],
+                                                   const double ph[NQ],
+                                                   const double jr[NQ][3], int a, int b,
+                                                   double rho_ln, double izln, double gm1i,
+                                                   double acc[NQ][5])
+{
+    const double n[3] = {0.5 * (jr[a][0] + jr[b][0]), 0.5 * (jr[a][1] + jr[b][1]),
+                         0.5 * (jr[a][2] + jr[b][2])};
+    double S[5];
+    sym_flux_vec(nd[a], nd[b], rho_ln, izln, n, 0.5 * (ph[a] + ph[b]), gm1i, S);
+    const double tab = tb.T[a][b], tba = tb.T[b][a];
+    const double X = 0.25 * rho_ln * (nd[a].z + nd[b].z) * (ph[b] - ph[a]);
+    const double ga = X * nd[a].zi, gb = X * nd[b].zi;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        acc[a][v] -= tab * S[v];
+        acc[b][v] -= tba * S[v];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        acc[a][1 + d] -= tab * (n[d] * ga);
+        acc[b][1 + d] += tba * (n[d] * gb);
+    }
+}
+
 // Face flux along the unnormalised outward normal Nv = s J a^r at a face
 // node (phi on both sides): the EC flux along Nv minus the Rusanov term
 // |Nv| lambda/2 (q+ - q-), lambda = max(|u.n| + c) with n = Nv/|Nv|.
@@ -169,29 +213,36 @@ __device__ __forceinline__ void line_terms_curved(const CurvedParams &C, const O
     }
 
     if (P.mask & TERM_VOL) {
+        double xr[NQ], xz[NQ];
 #pragma unroll
-        for (int a = 0; a < NQ; ++a) {
+        for (int t = 0; t < NQ; ++t) {
+            xr[t] = nd[t].r;
+            xz[t] = nd[t].z;
+        }
+        const bool need_r = line_spread<NQ>(xr), need_z = line_spread<NQ>(xz);
+        // wave-uniform choice: the series-only loop when no line of the wave
+        // can reach the log branch
+        if (__ballot(need_r || need_z) == 0) {
 #pragma unroll
-            for (int b = a + 1; b < NQ; ++b) {
-                const double n[3] = {0.5 * (jr[a][0] + jr[b][0]), 0.5 * (jr[a][1] + jr[b][1]),
-                                     0.5 * (jr[a][2] + jr[b][2])};
-                double rho_ln, izln, S[5];
-                pair_log_means(nd[a], nd[b], P, rho_ln, izln);
-                sym_flux_vec(nd[a], nd[b], rho_ln, izln, n, 0.5 * (ph[a] + ph[b]), P.gm1i, S);
-                const double tab = tb.T[a][b], tba = tb.T[b][a];
-                // gravity G_ab = rho_hat [[phi]]/2 along n, rho_hat = {{b}} {{rho}}_log / b_a;
-                // partner G_ba = -G_ab z_a / z_b
-                const double X = 0.25 * rho_ln * (nd[a].z + nd[b].z) * (ph[b] - ph[a]);
-                const double ga = X * nd[a].zi, gb = X * nd[b].zi;
+            for (int a = 0; a < NQ; ++a) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    acc[a][v] -= tab * S[v];
-                    acc[b][v] -= tba * S[v];
+                for (int b = a + 1; b < NQ; ++b) {
+                    double rho_ln, izln;
+                    pair_log_means_series(nd[a], nd[b], rho_ln, izln);
+                    curved_pair_shares<NQ>(tb, nd, ph, jr, a, b, rho_ln, izln, P.gm1i, acc);
                 }
+            }
+        } else {
+            double lr[NQ], lz[NQ];
+            line_logs<NQ>(xr, need_r, 1.0, lr);
+            line_logs<NQ>(xz, need_z, P.lnz_scale, lz);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    acc[a][1 + d] -= tab * (n[d] * ga);
-                    acc[b][1 + d] += tba * (n[d] * gb);
+            for (int a = 0; a < NQ; ++a) {
+#pragma unroll
+                for (int b = a + 1; b < NQ; ++b) {
+                    const double rho_ln = log_mean(nd[a].r, nd[b].r, lr[a], lr[b]);
+                    const double izln = inv_log_mean(nd[a].z, nd[b].z, lz[a], lz[b]);
+                    curved_pair_shares<NQ>(tb, nd, ph, jr, a, b, rho_ln, izln, P.gm1i, acc);
                 }
             }
         }
