@@ -42,7 +42,8 @@
  *     smooth displacement that vanishes on the box faces; metric terms in
  *     Kopriva's conservative curl form, volume flux with averaged metrics,
  *     face flux along the contravariant normal (Sec. 3: the metric terms G
- *     and the surface terms of the semi-discrete form);
+ *     and the surface terms of the semi-discrete form), with the matrix
+ *     dissipation written for a general unit normal;
  *   - time step: dt = CFL / ((N+1) max_a sum_r (|u_r| + c) / h_r).
  */
 #include <math.h>
@@ -322,7 +323,6 @@ void *oracle_mesh_create_warped(int N, const int *K, const double *lo, const dou
                                 const int *periodic, double gamma, double gas_R, double grav,
                                 double cor_f, int surf, const double *warp)
 {
-    if (surf == SURF_MATRIX) return NULL; /* general-normal matrix dissipation: not built */
     omesh *m = (omesh *)oracle_mesh_create(N, K, lo, hi, periodic, gamma, gas_R, grav, cor_f,
                                            surf);
     if (!m) return NULL;
@@ -563,6 +563,76 @@ static void matrix_dissipation(int r, const double qm[5], const double qp[5], do
     D[4] += phi * D[0];
 }
 
+/* The matrix dissipation above for a general unit normal n (curved faces).
+ * The acoustic and entropy eigenvectors keep their form with n in place of
+ * e_r.  The two shear eigenvectors (0, t, u_hat.t) span the tangent plane;
+ * whatever tangents are chosen, together they contribute
+ *   |u_n| p_hat (0, P w, u_hat . P w),   w = [[v]]_m + u_hat [[v]]_5,
+ * with P = I - n n^T the projector onto the tangent plane, so no tangents are
+ * formed.  For n = e_r this is matrix_dissipation(r, ...). */
+static void matrix_dissipation_vec(const double nv[3], const double qm[5], const double qp[5],
+                                   double phi, double gamma, double D[5])
+{
+    double gm1 = gamma - 1.0;
+    double rm = qm[0], rp = qp[0], um[3], up[3];
+    for (int c = 0; c < 3; ++c) {
+        um[c] = qm[1 + c] / rm;
+        up[c] = qp[1 + c] / rp;
+    }
+    double pm = pressure(qm, phi, gamma), pp = pressure(qp, phi, gamma);
+    double bm = rm / (2.0 * pm), bp = rp / (2.0 * pp);
+    double uum = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+    double uup = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+    double rho_hat = oracle_logmean(rm, rp);
+    double b_ln = oracle_logmean(bm, bp);
+    double uh[3];
+    for (int c = 0; c < 3; ++c) uh[c] = 0.5 * (um[c] + up[c]);
+    double p_hat = 0.5 * (rm + rp) / (2.0 * 0.5 * (bm + bp));
+    double u2bar = 2.0 * (uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2]) - 0.5 * (uum + uup);
+    double h_hat = gamma / (2.0 * gm1 * b_ln) + 0.5 * u2bar;
+    double a_hat = sqrt(gamma * p_hat / rho_hat);
+    double ds = log(pp / pm) - gamma * log(rp / rm);
+    double dv[5];
+    dv[0] = -ds / gm1 - (bp * uup - bm * uum);
+    for (int c = 0; c < 3; ++c) dv[1 + c] = 2.0 * (bp * up[c] - bm * um[c]);
+    dv[4] = -2.0 * (bp - bm);
+
+    double un = uh[0] * nv[0] + uh[1] * nv[1] + uh[2] * nv[2];
+    /* acoustic (-), entropy and acoustic (+) eigenvectors as columns */
+    double Rm[5][3];
+    Rm[0][0] = Rm[0][1] = Rm[0][2] = 1.0;
+    for (int c = 0; c < 3; ++c) {
+        Rm[1 + c][0] = uh[c] - a_hat * nv[c];
+        Rm[1 + c][1] = uh[c];
+        Rm[1 + c][2] = uh[c] + a_hat * nv[c];
+    }
+    Rm[4][0] = h_hat - a_hat * un;
+    Rm[4][1] = 0.5 * u2bar;
+    Rm[4][2] = h_hat + a_hat * un;
+    double lam[3] = {fabs(un - a_hat), fabs(un), fabs(un + a_hat)};
+    double tsc[3] = {rho_hat / (2.0 * gamma), rho_hat * gm1 / gamma, rho_hat / (2.0 * gamma)};
+    double w[3];
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+        for (int v = 0; v < 5; ++v) acc += Rm[v][k] * dv[v];
+        w[k] = lam[k] * tsc[k] * acc;
+    }
+    for (int v = 0; v < 5; ++v) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += Rm[v][k] * w[k];
+        D[v] = acc;
+    }
+    /* shear waves through the tangent projector */
+    double wv[3], Pw[3];
+    for (int c = 0; c < 3; ++c) wv[c] = dv[1 + c] + uh[c] * dv[4];
+    double nw = wv[0] * nv[0] + wv[1] * nv[1] + wv[2] * nv[2];
+    for (int c = 0; c < 3; ++c) Pw[c] = wv[c] - nv[c] * nw;
+    double sh = fabs(un) * p_hat;
+    for (int c = 0; c < 3; ++c) D[1 + c] += sh * Pw[c];
+    D[4] += sh * (uh[0] * Pw[0] + uh[1] * Pw[1] + uh[2] * Pw[2]);
+    D[4] += phi * D[0];
+}
+
 /* Normal face flux F* . n for the face with outward normal n = s e_r (s = +-1):
  * s f_r(q-, q+) - lambda/2 (q+ - q-) with lambda = max(|u.n| + c) (Rusanov),
  * s f_r(q-, q+) - D/2 with the matrix dissipation above, or without
@@ -592,8 +662,9 @@ void oracle_surface_flux(int r, int s, const double qm[5], const double qp[5], d
 
 /* Face flux along a general (unnormalised) normal Nv = s J a^r of a curved
  * element: sum_d Nv_d f_d(q-, q+) minus the Rusanov dissipation
- * |Nv| lambda/2 (q+ - q-), lambda = max(|u.n| + c) with n = Nv/|Nv|, or
- * without dissipation (EC).  Faces have phi+ = phi-. */
+ * |Nv| lambda/2 (q+ - q-), lambda = max(|u.n| + c) with n = Nv/|Nv|, minus
+ * |Nv| D(n)/2 with the matrix dissipation for the unit normal n, or without
+ * dissipation (EC).  Faces have phi+ = phi-. */
 void oracle_surface_flux_vec(const double Nv[3], const double qm[5], const double qp[5],
                              double phim, double phip, double gamma, int surf, double Fn[5])
 {
@@ -603,8 +674,14 @@ void oracle_surface_flux_vec(const double Nv[3], const double qm[5], const doubl
         oracle_two_point_flux(d, qm, qp, phim, phip, gamma, F);
         for (int v = 0; v < 5; ++v) Fn[v] += Nv[d] * F[v];
     }
-    if (surf != SURF_RUSANOV) return;
+    if (surf == SURF_EC) return;
     double nrm = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+    if (surf == SURF_MATRIX) {
+        double nu[3] = {Nv[0] / nrm, Nv[1] / nrm, Nv[2] / nrm}, D[5];
+        matrix_dissipation_vec(nu, qm, qp, phim, gamma, D);
+        for (int v = 0; v < 5; ++v) Fn[v] -= 0.5 * nrm * D[v];
+        return;
+    }
     double lam = 0.0;
     const double *qs[2] = {qm, qp};
     double phis[2] = {phim, phip};

@@ -188,11 +188,113 @@ def test_density_wave_convergence_on_curved_mesh():
     assert min(rates) >= N - 0.5, (errs, rates)
 
 
-def test_matrix_dissipation_on_curved_mesh_is_rejected():
-    spec = W.MeshSpec(3, (2, 2, 2), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 0),
+def _random_state(rng, phi):
+    rho = rng.uniform(0.05, 1.5)
+    u = rng.uniform(-60, 60, 3)
+    p = rho * 287.0 * rng.uniform(200, 320)
+    return np.array([rho, *(rho * u), p / (G - 1) + 0.5 * rho * (u @ u) + rho * phi])
+
+
+def _unit(rng):
+    v = rng.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def _matrix_diss_vec(nu, qm, qp, phi):
+    Fm = O.surface_flux_vec(nu, qm, qp, phi, phi, G, O.SURF_MATRIX)
+    Fe = O.surface_flux_vec(nu, qm, qp, phi, phi, G, O.SURF_EC)
+    return -2.0 * (Fm - Fe)
+
+
+def test_general_normal_matrix_dissipation_reduces_to_axis_form():
+    rng = np.random.default_rng(21)
+    for _ in range(40):
+        phi = rng.uniform(0, 3e5)
+        qm, qp = _random_state(rng, phi), _random_state(rng, phi)
+        for r in range(3):
+            for s in (-1, 1):
+                scale = rng.uniform(0.5, 2.0)
+                Nv = np.zeros(3)
+                Nv[r] = s * scale
+                a = O.surface_flux_vec(Nv, qm, qp, phi, phi, G, O.SURF_MATRIX)
+                b = scale * O.surface_flux(r, s, qm, qp, phi, phi, G, O.SURF_MATRIX)
+                assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
+
+
+def test_general_normal_matrix_dissipation_small_jump_and_stability():
+    # for a random unit normal: the small-jump limit |A_n| [[q]] with
+    # A_n = sum_d n_d df_d/dq (complex-step Jacobians of the test's own
+    # physical flux, numpy's eigen-decomposition), and [[v]].D > 0
+    from tests.test_oracle_flux import _jacobian_complex_step, _v_complex_step
+    rng = np.random.default_rng(22)
+    for _ in range(30):
+        phi = rng.uniform(0, 3e5)
+        nu = _unit(rng)
+        q = _random_state(rng, phi)
+        qp = q + 1e-6 * (_random_state(rng, phi) - q)
+        qbar = 0.5 * (q + qp)
+        A = sum(nu[d] * _jacobian_complex_step(d, qbar, phi) for d in range(3))
+        lam, V = np.linalg.eig(A)
+        absA = (V @ np.diag(np.abs(lam)) @ np.linalg.inv(V)).real
+        D = _matrix_diss_vec(nu, q, qp, phi)
+        scale = np.abs(absA) @ np.abs(qp - q)
+        assert np.all(np.abs(D - absA @ (qp - q)) <= 1e-5 * scale)
+        qm, qq = _random_state(rng, phi), _random_state(rng, phi)
+        dv = _v_complex_step(qq, phi) - _v_complex_step(qm, phi)
+        Dl = _matrix_diss_vec(nu, qm, qq, phi)
+        assert dv @ Dl > 0.0
+
+
+def test_general_normal_matrix_dissipation_is_rotation_equivariant():
+    # rotating both states' momenta and the normal rotates the momentum part
+    # of D and leaves mass and energy unchanged (pins the tangent projector)
+    rng = np.random.default_rng(23)
+    for _ in range(40):
+        phi = rng.uniform(0, 3e5)
+        qm, qp = _random_state(rng, phi), _random_state(rng, phi)
+        nu = _unit(rng)
+        Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        rot = lambda q: np.array([q[0], *(Q @ q[1:4]), q[4]])
+        D = _matrix_diss_vec(nu, qm, qp, phi)
+        Dr = _matrix_diss_vec(Q @ nu, rot(qm), rot(qp), phi)
+        sc = np.abs(D).max()
+        assert abs(Dr[0] - D[0]) <= 1e-11 * sc and abs(Dr[4] - D[4]) <= 1e-11 * sc
+        assert np.allclose(Dr[1:4], Q @ D[1:4], rtol=0, atol=1e-11 * sc)
+
+
+def test_matrix_dissipation_on_curved_mesh():
+    # free stream, isothermal balance and conservation hold with matrix
+    # dissipation on curved faces; entropy production EC = 0 > matrix > Rusanov
+    spec = W.MeshSpec(3, (3, 2, 2), (0, 0, 0), (1000.0, 800.0, 1200.0), (1, 1, 1), grav=0.0,
                       surface_flux=O.SURF_MATRIX)
-    with pytest.raises(ValueError):
-        _mesh(spec)
+    m = _mesh(spec)
+    q = W.constant_state(m.ne, m.Np)
+    r, g = m.rhs(q, gross=True)
+    assert np.all(_rel_gross(r, 0 * r, g) < 1e-14)
+    spec_b = W.MeshSpec(3, (2, 2, 4), (0, 0, 0), (2000.0, 2000.0, 30000.0), (1, 1, 0),
+                        surface_flux=O.SURF_MATRIX)
+    mb = _mesh(spec_b)
+    qb = W.state_iso_rest(mb.coords(), spec_b, T=250.0)
+    r, g = mb.rhs(qb, gross=True)
+    assert np.all(_rel_gross(r, 0 * r, g) < 1e-14)
+    prod = {}
+    for surf in (O.SURF_EC, O.SURF_MATRIX, O.SURF_RUSANOV):
+        sp = W.MeshSpec(3, (3, 2, 2), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 1), grav=0.0,
+                        surface_flux=surf)
+        mm = _mesh(sp)
+        qq = _with_jumps(W.state_iso_pert(mm.coords(), sp, seed=8, amp_rho=5e-2, amp_u=20.0), 8)
+        rr, gg = mm.rhs(qq, gross=True)
+        v = _entropy_vars_field(qq, mm.phi())
+        _, Jd = mm.metrics()
+        wq = (Jd * _quad_weights(mm)[None, :])[:, None, :]
+        prod[surf] = (wq * v * rr).sum()
+        scale = (wq * np.abs(v) * gg).sum()
+        if surf == O.SURF_MATRIX:
+            for c in (0, 4):
+                tot = (wq[:, 0] * rr[:, c]).sum()
+                assert abs(tot) <= 1e-15 * (wq[:, 0] * gg[:, c]).sum()
+    assert abs(prod[O.SURF_EC]) <= 1e-14 * scale
+    assert prod[O.SURF_RUSANOV] < prod[O.SURF_MATRIX] < -1e-6 * scale
 
 
 def test_general_normal_face_flux_reduces_to_axis_flux():
