@@ -84,8 +84,8 @@ typedef struct esdg_mesh *esdg_mesh_t;
  *                periodic faces).  Metric terms in the conservative curl
  *                form, built on the host at creation (88 B per node of
  *                device geometry plus 24 B of coordinates).  FP64 only,
- *                Rusanov or EC faces, not packable; a warp that folds an
- *                element (J <= 0) is rejected (ESDG_EINVAL).
+ *                not packable; a warp that folds an element (J <= 0) is
+ *                rejected (ESDG_EINVAL).
  *   warp[3]      the warp amplitudes (fractions of the box lengths) */
 typedef struct {
     int32_t N;

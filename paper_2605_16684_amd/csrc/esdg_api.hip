@@ -713,19 +713,17 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         return fail(ESDG_EINVAL, "unknown surface flux %d", d->surface_flux);
     if (d->precision != ESDG_FP64 && d->precision != ESDG_FP32_MIXED)
         return fail(ESDG_EINVAL, "unknown precision %d", d->precision);
-    if (d->precision == ESDG_FP32_MIXED) {
-        int rc0;
-        if ((rc0 = check_ptr(d->ref_rho, "ref_rho")) || (rc0 = check_ptr(d->ref_p, "ref_p")))
-            return rc0;
-    }
     if (d->curved != 0 && d->curved != 1) return fail(ESDG_EINVAL, "curved must be 0 or 1");
     if (d->curved) {
         if (d->precision != ESDG_FP64)
             return fail(ESDG_EINVAL, "curved meshes run in FP64 only");
-        if (d->surface_flux == ESDG_SURF_MATRIX)
-            return fail(ESDG_EINVAL, "matrix dissipation on curved meshes is not built");
         for (int k = 0; k < 3; ++k)
             if (!std::isfinite(d->warp[k])) return fail(ESDG_EINVAL, "warp[%d] is not finite", k);
+    }
+    if (d->precision == ESDG_FP32_MIXED) {
+        int rc0;
+        if ((rc0 = check_ptr(d->ref_rho, "ref_rho")) || (rc0 = check_ptr(d->ref_p, "ref_p")))
+            return rc0;
     }
     const int epw = d->epw ? d->epw : default_epw(d->N, d->precision);
     if (d->curved ? !find_curved_variant(d->N, epw) : !has_variant(d->precision, d->N, epw))

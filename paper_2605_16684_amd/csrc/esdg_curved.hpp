@@ -127,9 +127,68 @@ __device__ __forceinline__ void curved_pair_shares(const OrderTables &tb, const 
     }
 }
 
+// Matrix dissipation for a general unit normal nu: the operator of
+// matrix_dissipation<R> with nu in place of e_R; the two shear waves enter
+// through the tangent projector P = I - nu nu^T,
+//   |u_n| p_hat (0, P w, u_hat . P w),  w = [[v]]_m + u_hat [[v]]_5,
+// which does not depend on the tangents one would choose.
+__device__ __forceinline__ void matrix_dissipation_vec(const Node &a, const Node &b,
+                                                       double rho_ln, double izln, double phi,
+                                                       const double nu[3],
+                                                       const StageParams &P, double D[5])
+{
+    const double g = P.gamma, gm1i = P.gm1i;
+    const double u[3] = {a.h0 + b.h0, a.h1 + b.h1, a.h2 + b.h2};
+    const double ka = a.h0 * a.h0 + a.h1 * a.h1 + a.h2 * a.h2;
+    const double kb = b.h0 * b.h0 + b.h1 * b.h1 + b.h2 * b.h2;
+    const double u2bar = 2.0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 2.0 * (ka + kb);
+    const double phat = fdiv(a.r + b.r, a.z + b.z);
+    const double hhat = g * gm1i * izln + 0.5 * u2bar;
+    const double ahat = sqrt_pos(g * fdiv(phat, rho_ln));
+    const double dz = b.z - a.z;
+    double dv[5];
+    {
+        // jumps of products without FMA contraction (they must vanish
+        // exactly where the two sides agree)
+#pragma clang fp contract(off)
+        const double zk_a = a.z * ka, zk_b = b.z * kb;
+        dv[0] = fdiv(b.r - a.r, rho_ln) + gm1i * (dz * izln) - 2.0 * (zk_b - zk_a);
+        dv[1] = 2.0 * (b.z * b.h0 - a.z * a.h0);
+        dv[2] = 2.0 * (b.z * b.h1 - a.z * a.h1);
+        dv[3] = 2.0 * (b.z * b.h2 - a.z * a.h2);
+    }
+    dv[4] = -dz;
+    const double un = u[0] * nu[0] + u[1] * nu[1] + u[2] * nu[2];
+    const double dvn = dv[1] * nu[0] + dv[2] * nu[1] + dv[3] * nu[2];
+    const double c0 = dv[0] + u[0] * dv[1] + u[1] * dv[2] + u[2] * dv[3] + hhat * dv[4];
+    const double an = ahat * (dvn + un * dv[4]);
+    const double ta = rho_ln * (0.5 / g);
+    const double te = rho_ln * (g - 1.0) / g;
+    const double aun = fabs(un);
+    const double s0 = fabs(un - ahat) * ta * (c0 - an);
+    const double s4 = fabs(un + ahat) * ta * (c0 + an);
+    const double s1 = aun * te * (c0 - (hhat - 0.5 * u2bar) * dv[4]);
+    const double sa = s0 + s1 + s4, sd = s4 - s0;
+    double w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = dv[1 + c] + u[c] * dv[4];
+    const double nw = w[0] * nu[0] + w[1] * nu[1] + w[2] * nu[2];
+    const double sh = aun * phat;
+    double uPw = 0.0;
+    D[0] = sa;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double Pw = w[c] - nu[c] * nw;
+        D[1 + c] = u[c] * sa + ahat * nu[c] * sd + sh * Pw;
+        uPw += u[c] * Pw;
+    }
+    D[4] = hhat * (s0 + s4) + ahat * un * sd + 0.5 * u2bar * s1 + sh * uPw + phi * sa;
+}
+
 // Face flux along the unnormalised outward normal Nv = s J a^r at a face
 // node (phi on both sides): the EC flux along Nv minus the Rusanov term
-// |Nv| lambda/2 (q+ - q-), lambda = max(|u.n| + c) with n = Nv/|Nv|.
+// |Nv| lambda/2 (q+ - q-), lambda = max(|u.n| + c) with n = Nv/|Nv|, or
+// minus |Nv| D(n)/2 with the matrix dissipation, or nothing (EC).
 __device__ __forceinline__ void face_flux_vec(const Node &a, const Cons &qm, const Cons &qp,
                                               double phi, const double Nv[3],
                                               const StageParams &P, double Fn[5])
@@ -140,6 +199,16 @@ __device__ __forceinline__ void face_flux_vec(const Node &a, const Cons &qm, con
     pair_log_means(a, b, P, rho_ln, izln);
     double S[5];
     sym_flux_vec(a, b, rho_ln, izln, Nv, phi, P.gm1i, S);
+    if (P.surf == SURF_MATRIX) {
+        const double nrm = sqrt_pos(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+        const double inrm = frcp(nrm);
+        const double nu[3] = {Nv[0] * inrm, Nv[1] * inrm, Nv[2] * inrm};
+        double D[5];
+        matrix_dissipation_vec(a, b, rho_ln, izln, phi, nu, P, D);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fn[v] = S[v] - 0.5 * nrm * D[v];
+        return;
+    }
     double hl = 0.0;
     if (P.surf == SURF_RUSANOV) {
         const double n2 = Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2];
