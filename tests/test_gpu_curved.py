@@ -183,6 +183,35 @@ def test_curved_matrix_dissipation_vanishes_exactly_where_states_agree():
     assert abs(e[1]) < 1e-10 * abs(e[2])
 
 
+@pytest.mark.parametrize("mask", [1, 2, 4, 3, 6])
+def test_curved_term_split_parity(mask):
+    # volume, face and source terms separately (and in pairs) against the
+    # oracle's term split on the curved mesh
+    esdg = _esdg()
+    spec = W.MeshSpec(3, (3, 2, 2), *_BOX, (1, 0, 0), coriolis_f=1e-4, warp=WARP)
+    om = _oracle_mesh(spec)
+    q = _with_jumps(W.state_iso_pert(om.coords(), spec, seed=4), 4)
+    r_or = om.rhs(q, mask=mask)
+    _, g = om.rhs(q, gross=True)
+    m = esdg.Mesh(spec)
+    r = m.rhs_terms(torch.from_numpy(q).cuda(), mask).cpu().numpy()
+    eg = err_gross(r, r_or, g)
+    print(f"[curved mask {mask}] err/gross={np.array2string(eg, precision=2)}", flush=True)
+    assert np.all(eg <= TOL_RHS), eg
+
+
+def test_curved_mesh_is_not_packed():
+    esdg = _esdg()
+    spec = W.MeshSpec(3, (2, 2, 2), *_BOX, (1, 1, 0), warp=WARP)
+    m = esdg.Mesh(spec)
+    q0 = m.empty()
+    q0.copy_(torch.from_numpy(W.state_iso_pert(_oracle_mesh(spec).coords(), spec, seed=1)))
+    pack = esdg.Pack()
+    with pytest.raises(esdg.EsdgError, match="curved"):
+        pack.set_members([m], [q0], [torch.empty_like(q0)], [torch.zeros_like(q0)], [1e-3], [0])
+    pack.close()
+
+
 def test_folding_warp_is_rejected():
     esdg = _esdg()
     spec = W.MeshSpec(4, (2, 2, 2), *_BOX, (1, 1, 0), warp=(0.6, 0.6, 0.6))
