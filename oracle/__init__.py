@@ -66,6 +66,7 @@ def _load():
         "oracle_entropy": (C.c_int, [C.c_void_p, _dp, _dp]),
         "oracle_cfl_dt": (C.c_double, [C.c_void_p, _dp, C.c_double]),
         "oracle_num_threads": (C.c_int, []),
+        "oracle_set_num_threads": (None, [C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -90,6 +91,10 @@ def _vec(x, n=5):
 
 def num_threads() -> int:
     return _lib.oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _lib.oracle_set_num_threads(int(n))
 
 
 def lgl(N: int):

@@ -1197,3 +1197,14 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the parallel loops that follow (the CPU baseline times the
+ * oracle on all host cores and on one). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
