@@ -202,10 +202,37 @@ def serving_block(torch, throughput, n=96, steps=50, budget_gb=24.0, load=1.2, s
     return out
 
 
-def surface_block(esdg, torch, spec, q, dt, steps, epw, value, t_rhs):
+def oracle_sample(wl, spec, seconds, n_el=512, seed=1):
+    """The oracle on a bounded sample of a workload variant (RHS evaluations
+    of elements 0..n_el-1 for about `seconds`), beside a GPU leg."""
+    import numpy as np
+    import oracle as O
+    from paper_2605_16684_amd import workloads as W
+    s = spec
+    om = O.Mesh(s.N, s.K, s.lo, s.hi, s.periodic, gamma=s.gamma, gas_R=s.gas_R, grav=s.grav,
+                coriolis_f=s.coriolis_f, surface_flux=s.surface_flux, warp=s.warp)
+    q = W.make_state(wl.kind, om.coords(), s, seed=seed)
+    el = np.arange(min(om.ne, n_el), dtype=np.int64)
+    om.rhs_elems(q, el)
+    t0 = time.perf_counter()
+    evals = 0
+    while True:
+        om.rhs_elems(q, el)
+        evals += 1
+        d = time.perf_counter() - t0
+        if d >= seconds:
+            break
+    return {"value": len(el) * om.Np * evals / d, "unit": "DOF*RHS/s", "cores": O.num_threads(),
+            "kind": "oracle", "sample": f"{evals} RHS evaluations of elements 0..{len(el) - 1}, "
+                                        f"{d:.1f} s"}
+
+
+def surface_block(esdg, torch, perfmodel, wl, spec, q, dt, steps, epw, value, t_rhs,
+                  cpu_seconds):
     """The same workload and state with matrix-dissipation faces (the paper's
     interface flux): whole LSRK(5,4) steps and RHS-only launches, beside the
-    Rusanov figures of the headline run."""
+    Rusanov figures of the headline run, with the stage launch's algorithmic
+    bytes against the HBM peak and the oracle timed on a sample."""
     stream = torch.cuda.current_stream()
     m = esdg.Mesh(replace(spec, surface_flux=esdg.SURF_MATRIX), epw=epw)
     qm = q.clone()
@@ -232,16 +259,23 @@ def surface_block(esdg, torch, spec, q, dt, steps, epw, value, t_rhs):
     t_r = e0.elapsed_time(e1) * 1e-3 / nr
     nn = m.n_nodes
     v = nn * 5.0 * steps / (ms * 1e-3)
+    t_launch = ms * 1e-3 / (5 * steps)
+    gbs = perfmodel.bytes_per_node(spec.N) * nn / t_launch / 1e9
     m.close()
-    return {"surface_flux": "matrix dissipation", "steps": steps, "ms_per_step": ms / steps,
-            "dof_rhs_per_s": v, "vs_rusanov": v / value,
-            "rhs_only_launch_ms": t_r * 1e3, "rhs_only_vs_rusanov": t_rhs / t_r}
+    out = {"surface_flux": "matrix dissipation", "steps": steps, "ms_per_step": ms / steps,
+           "dof_rhs_per_s": v, "vs_rusanov": v / value, "launch_ms": t_launch * 1e3,
+           "achieved_gbs": gbs, "hbm_frac": gbs / perfmodel.HBM_PEAK_GBS,
+           "rhs_only_launch_ms": t_r * 1e3, "rhs_only_vs_rusanov": t_rhs / t_r}
+    if cpu_seconds > 0:
+        out["cpu_oracle"] = oracle_sample(wl, replace(spec, surface_flux=esdg.SURF_MATRIX),
+                                          cpu_seconds)
+    return out
 
 
 CURVED_WARP = (0.05, 0.04, 0.03)
 
 
-def curved_block(esdg, W, torch, perfmodel, wl, steps, value):
+def curved_block(esdg, W, torch, perfmodel, wl, steps, value, cpu_seconds):
     """The same workload on the warped box (curved hexahedra, per-node
     metric terms): whole LSRK(5,4) steps and RHS launches, with the curved
     kernel's algorithmic bytes (state plus 88 B of geometry per node)."""
@@ -277,12 +311,15 @@ def curved_block(esdg, W, torch, perfmodel, wl, steps, value):
     gbs = perfmodel.bytes_per_node_curved(N) * nn / t_launch / 1e9
     v = nn * 5.0 * steps / (ms * 1e-3)
     m.close()
-    return {"warp": list(CURVED_WARP), "kernel": f"stage_curved<{N + 1},{epw}>",
-            "steps": steps, "ms_per_step": ms / steps, "dof_rhs_per_s": v,
-            "vs_affine": v / value, "launch_ms": t_launch * 1e3,
-            "algorithmic_bytes_per_launch": perfmodel.bytes_per_node_curved(N) * nn,
-            "achieved_gbs": gbs, "hbm_frac": gbs / perfmodel.HBM_PEAK_GBS,
-            "rhs_only_launch_ms": t_r * 1e3}
+    out = {"warp": list(CURVED_WARP), "kernel": f"stage_curved<{N + 1},{epw}>",
+           "steps": steps, "ms_per_step": ms / steps, "dof_rhs_per_s": v,
+           "vs_affine": v / value, "launch_ms": t_launch * 1e3,
+           "algorithmic_bytes_per_launch": perfmodel.bytes_per_node_curved(N) * nn,
+           "achieved_gbs": gbs, "hbm_frac": gbs / perfmodel.HBM_PEAK_GBS,
+           "rhs_only_launch_ms": t_r * 1e3}
+    if cpu_seconds > 0:
+        out["cpu_oracle"] = oracle_sample(wl, spec, cpu_seconds)
+    return out
 
 
 def sweep_block(esdg, W, torch, orders=(3, 4, 5, 7), sizes=(2, 4, 8, 12, 16, 24, 32, 40),
@@ -482,14 +519,16 @@ def main():
     del dq, r
     if args.surface == "rusanov" and not args.no_matrix_leg:
         log("[bench] matrix-dissipation faces ...")
-        out["surface_matrix"] = surface_block(esdg, torch, spec, q, dt, 2 * max(1, min(K, 40) // 2),
-                                              args.epw, value, t_rhs)
+        out["surface_matrix"] = surface_block(esdg, torch, perfmodel, wl, spec, q, dt,
+                                              2 * max(1, min(K, 40) // 2), args.epw, value,
+                                              t_rhs, 0.0 if args.no_cpu else 3.0)
     del q
     torch.cuda.empty_cache()
     if args.surface == "rusanov" and not args.no_curved_leg:
         log("[bench] curved hexahedra ...")
         out["curved"] = curved_block(esdg, W, torch, perfmodel, wl,
-                                     2 * max(1, min(K, 40) // 2), value)
+                                     2 * max(1, min(K, 40) // 2), value,
+                                     0.0 if args.no_cpu else 3.0)
         torch.cuda.empty_cache()
     if not args.no_precision:
         log("[bench] FP64 vs FP32-mixed ...")
