@@ -105,9 +105,11 @@ def test_zero_warp_curved_path_equals_affine_path(N):
     assert np.all(eg <= 1e-14), eg
 
 
-def test_curved_lsrk_100_steps_parity():
+@pytest.mark.parametrize("surf", [0, 2], ids=["rusanov", "matrix"])
+def test_curved_lsrk_100_steps_parity(surf):
     esdg = _esdg()
-    spec = W.MeshSpec(3, (4, 4, 4), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 0), warp=WARP)
+    spec = W.MeshSpec(3, (4, 4, 4), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 0), warp=WARP,
+                      surface_flux=surf)
     om = _oracle_mesh(spec)
     q0 = W.state_iso_pert(om.coords(), spec, seed=1)
     dt = om.cfl_dt(q0, 0.5)
@@ -117,7 +119,8 @@ def test_curved_lsrk_100_steps_parity():
     dq = torch.zeros_like(qg)
     m.lsrk_run(qg, dq, dt, 100)
     e = err_net(qg.cpu().numpy(), q_or)
-    print(f"[curved lsrk100] state rel L2 per var {np.array2string(e, precision=2)}", flush=True)
+    print(f"[curved lsrk100 surf={surf}] state rel L2 per var {np.array2string(e, precision=2)}",
+          flush=True)
     assert np.all(e <= TOL_STATE), e
     # eager steps give the graph's bits
     qe = torch.from_numpy(q0).cuda()
