@@ -100,21 +100,21 @@ __device__ __forceinline__ void pair_log_means_series(const Node &a, const Node 
 }
 
 // Shares of one pair (a, b) of a line: the flux along the averaged J a^r and
-// the gravity term along it (partner G_ba = -G_ab z_a / z_b).
+// the gravity term along it (partner G_ba = -G_ab z_a / z_b).  jh holds the
+// halved metric terms J a^r / 2 of the line's nodes.
 template <int NQ>
 __device__ __forceinline__ void curved_pair_shares(const OrderTables &tb, const Node nd[NQ],
                                                    const double ph[NQ],
-                                                   const double jr[NQ][3], int a, int b,
+                                                   const double jh[NQ][3], int a, int b,
                                                    double rho_ln, double izln, double gm1i,
                                                    double acc[NQ][5])
 {
-    const double n[3] = {0.5 * (jr[a][0] + jr[b][0]), 0.5 * (jr[a][1] + jr[b][1]),
-                         0.5 * (jr[a][2] + jr[b][2])};
+    const double n[3] = {jh[a][0] + jh[b][0], jh[a][1] + jh[b][1], jh[a][2] + jh[b][2]};
     double S[5];
     sym_flux_vec(nd[a], nd[b], rho_ln, izln, n, 0.5 * (ph[a] + ph[b]), gm1i, S);
     const double tab = tb.T[a][b], tba = tb.T[b][a];
     const double X = 0.25 * rho_ln * (nd[a].z + nd[b].z) * (ph[b] - ph[a]);
-    const double ga = X * nd[a].zi, gb = X * nd[b].zi;
+    const double tga = tab * (X * nd[a].zi), tgb = tba * (X * nd[b].zi);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         acc[a][v] -= tab * S[v];
@@ -122,8 +122,8 @@ __device__ __forceinline__ void curved_pair_shares(const OrderTables &tb, const 
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        acc[a][1 + d] -= tab * (n[d] * ga);
-        acc[b][1 + d] += tba * (n[d] * gb);
+        acc[a][1 + d] -= tga * n[d];
+        acc[b][1 + d] += tgb * n[d];
     }
 }
 
@@ -248,7 +248,7 @@ __device__ __forceinline__ void line_terms_curved(const CurvedParams &C, const O
         load_cons(P.q_in, e, NQ3, n, qc[t]);
         ph[t] = C.phi[e * NQ3 + n];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) jr[t][d] = C.Ja[((e * 3 + R) * 3 + d) * NQ3 + n];
+        for (int d = 0; d < 3; ++d) jr[t][d] = 0.5 * C.Ja[((e * 3 + R) * 3 + d) * NQ3 + n];
     }
     const bool faces = (P.mask & TERM_FACE) != 0;
     Cons qp[2];
@@ -271,7 +271,7 @@ __device__ __forceinline__ void line_terms_curved(const CurvedParams &C, const O
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int t = side ? NQ - 1 : 0;
-            const double s = side ? 1.0 : -1.0;
+            const double s = side ? 2.0 : -2.0;  // jr holds J a^r / 2
             const double Nv[3] = {s * jr[t][0], s * jr[t][1], s * jr[t][2]};
             double Fn[5];
             face_flux_vec(nd[t], qc[t], qp[side], ph[t], Nv, P, Fn);
