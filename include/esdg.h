@@ -123,7 +123,8 @@ int esdg_mesh_info(esdg_mesh_t mesh, int64_t *n_elem, int64_t *n_nodes, int64_t 
 int esdg_set_stream(esdg_mesh_t mesh, void *hip_stream);
 
 /* Elements per workgroup the launches use (for autotuning); 0 restores the
- * default.  ESDG_EINVAL if the value has no compiled variant. */
+ * default.  ESDG_EINVAL if the value has no compiled variant (curved meshes
+ * compile only the default of each order). */
 int esdg_set_epw(esdg_mesh_t mesh, int32_t epw);
 
 /* Elements per workgroup currently used by the mesh's launches. */
@@ -192,8 +193,9 @@ const char *esdg_version(void);
 int esdg_lgl_tables(int32_t N, double *xi, double *w, double *D);
 
 /* Elements-per-workgroup values compiled for order N and a precision
- * (ESDG_FP64 or ESDG_FP32_MIXED): writes up to cap of them to out (may be
- * NULL) and returns their count, or a negative error.  Host-only. */
+ * (ESDG_FP64 or ESDG_FP32_MIXED) on the affine box: writes up to cap of them
+ * to out (may be NULL) and returns their count, or a negative error.
+ * Curved meshes use the FP64 default of each order only.  Host-only. */
 int esdg_epw_options(int32_t N, int32_t precision, int32_t *out, int32_t cap);
 
 /* ---- Packed multi-member stepping (ensemble serving) --------------------
