@@ -35,7 +35,10 @@ def traffic_record(kernel_name, workload):
     with open(path) as f:
         rec = json.load(f)
     ent = rec.get(workload, {}).get(kernel_name)
-    if not ent or ent.get("kernel_hash") != perfmodel.kernel_source_hash():
+    if not ent:
+        return None
+    names = perfmodel.kernel_sources(ent.get("kernel", kernel_name))
+    if ent.get("kernel_hash") != perfmodel.kernel_source_hash(names=names):
         return None
     return ent.get("bytes_per_launch")
 
@@ -316,6 +319,8 @@ def curved_block(esdg, W, torch, perfmodel, wl, steps, value, cpu_seconds):
            "vs_affine": v / value, "launch_ms": t_launch * 1e3,
            "algorithmic_bytes_per_launch": perfmodel.bytes_per_node_curved(N) * nn,
            "achieved_gbs": gbs, "hbm_frac": gbs / perfmodel.HBM_PEAK_GBS,
+           "traffic": traffic_record(f"void esdg::stage_curved<{N + 1}, {epw}, 1>"
+                                     "(esdg::CurvedParams)", f"{wl.name}_curved"),
            "rhs_only_launch_ms": t_r * 1e3}
     if cpu_seconds > 0:
         out["cpu_oracle"] = oracle_sample(wl, spec, cpu_seconds)

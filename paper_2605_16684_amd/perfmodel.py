@@ -84,6 +84,16 @@ def _code_only(text: str) -> str:
 FP64_STAGE_SOURCES = ("esdg_api.hip", "esdg_device.hpp")
 
 
+def kernel_sources(kernel_name: str):
+    """The sources a stage kernel is built from: the FP64 kernel's, plus the
+    curved or mixed-precision kernel's own header."""
+    if "stage_curved" in kernel_name:
+        return FP64_STAGE_SOURCES + ("esdg_curved.hpp",)
+    if "stage_mixed" in kernel_name:
+        return FP64_STAGE_SOURCES + ("esdg_mixed.hpp",)
+    return FP64_STAGE_SOURCES
+
+
 def kernel_source_hash(src_dir: str = _SRC_DIR, names=FP64_STAGE_SOURCES) -> str:
     """Hash of the code of the FP64 stage kernel's sources (comments and
     whitespace ignored): hardware counters taken for an older kernel are not

@@ -110,7 +110,9 @@ def cmd_traffic(a):
         ent = data.setdefault(a.workload, {})
         for name, r in rec.items():
             key = "stage_fp64" if (r["mode"] == "stage" and "stage_fp64" in name) else name
-            r = dict(r, kernel=name, kernel_hash=perfmodel.kernel_source_hash(),
+            r = dict(r, kernel=name,
+                     kernel_hash=perfmodel.kernel_source_hash(
+                         names=perfmodel.kernel_sources(name)),
                      fetch_factor=ff, write_factor=wf)
             ent[key] = r
         with open(a.json, "w") as f:
