@@ -434,6 +434,17 @@ def main():
     ms = e0.elapsed_time(e1)
     mesh.check()
     diag1 = mesh.entropy(q)
+    # five more timed windows of min(K, 200) steps after the reported run:
+    # their median and spread (the reported value is the first run)
+    Kr = 2 * max(1, min(K, 200) // 2)
+    reps = []
+    for _ in range(5):
+        e0.record(stream)
+        mesh.lsrk_run(q, dq, dt, Kr)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1) / Kr)
+    mesh.check()
 
     nn = mesh.n_nodes
     value = nn * 5.0 * K / (ms * 1e-3)
@@ -515,6 +526,9 @@ def main():
         "rhs_only": {"launch_ms": t_rhs * 1e3, "dof_rhs_per_s": nn / t_rhs,
                      "gbs": perfmodel.bytes_per_node(N, stage=False) * nn / t_rhs / 1e9,
                      "fp64_tflops": perfmodel.flops_per_node(N, stage=False) * nn / t_rhs / 1e12},
+        "repeats": {"n": len(reps), "steps": Kr, "ms_per_step_median": float(np.median(reps)),
+                    "ms_per_step_min": min(reps), "ms_per_step_max": max(reps),
+                    "dof_rhs_per_s_median": nn * 5.0 / (float(np.median(reps)) * 1e-3)},
         "conservation": {"mass_rel_drift": abs(diag1[1] - diag0[1]) / abs(diag0[1]),
                          "energy_rel_drift": abs(diag1[2] - diag0[2]) / abs(diag0[2]),
                          "entropy_rel_change": (diag1[0] - diag0[0]) / abs(diag0[0])},
