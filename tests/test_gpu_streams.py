@@ -1,0 +1,86 @@
+"""Stream binding of the library: every call runs on torch's current
+stream, so work issued under a side stream gives the default stream's bits,
+and two meshes stepping on two streams at once do not disturb each other
+(streams at the default priority)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_16684_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+WARP = (0.05, 0.04, 0.03)
+
+
+def _esdg():
+    from paper_2605_16684_amd import esdg
+    return esdg
+
+
+def _setup(spec, seed):
+    esdg = _esdg()
+    om = O.Mesh(spec.N, spec.K, spec.lo, spec.hi, spec.periodic, gamma=spec.gamma,
+                gas_R=spec.gas_R, grav=spec.grav, coriolis_f=spec.coriolis_f,
+                surface_flux=spec.surface_flux, warp=spec.warp)
+    q = torch.from_numpy(W.state_iso_pert(om.coords(), spec, seed=seed)).cuda()
+    m = esdg.Mesh(spec)
+    return m, q, m.cfl_dt(q, 0.5)
+
+
+@pytest.mark.parametrize("warp", [None, WARP], ids=["affine", "curved"])
+def test_side_stream_gives_the_default_streams_bits(warp):
+    spec = W.MeshSpec(4, (4, 3, 3), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 1, 0),
+                      coriolis_f=1e-4, warp=warp)
+    m, q, dt = _setup(spec, 3)
+    r0 = m.rhs(q)
+    qa, dqa = q.clone(), torch.zeros_like(q)
+    m.lsrk_run(qa, dqa, dt, 6)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        r1 = m.rhs(q)
+        qb, dqb = q.clone(), torch.zeros_like(q)
+        m.lsrk_run(qb, dqb, dt, 6)
+        m.lsrk_step(qb, dqb, dt)
+    s.synchronize()
+    assert torch.equal(r0, r1)
+    m.lsrk_step(qa, dqa, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(qa, qb)
+
+
+def test_two_meshes_step_concurrently_on_two_streams():
+    specs = [W.MeshSpec(3, (6, 5, 4), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 0, 0)),
+             W.MeshSpec(4, (4, 4, 3), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 1, 0), warp=WARP)]
+    runs = [_setup(sp, 5 + i) for i, sp in enumerate(specs)]
+    ref = []
+    for m, q, dt in runs:
+        qa, dqa = q.clone(), torch.zeros_like(q)
+        m.lsrk_run(qa, dqa, dt, 10)
+        ref.append(qa)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for (m, q, dt), s in zip(runs, streams):
+        with torch.cuda.stream(s):
+            qb, dqb = q.clone(), torch.zeros_like(q)
+            m.lsrk_run(qb, dqb, dt, 10)
+            outs.append(qb)
+    for s in streams:
+        s.synchronize()
+    for a, b in zip(ref, outs):
+        assert torch.equal(a, b)
+
+
+def test_nonphysical_state_is_reported_on_a_curved_mesh():
+    esdg = _esdg()
+    spec = W.MeshSpec(3, (3, 2, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 1, 0), warp=WARP)
+    m, q, _ = _setup(spec, 1)
+    q = q.clone()
+    q[5, 0, 7] = -1.0
+    m.rhs(q)
+    with pytest.raises(esdg.NonPhysicalState):
+        m.check()
+    m.check()
