@@ -215,6 +215,29 @@ def test_curved_mesh_is_not_packed():
     pack.close()
 
 
+def test_curved_mass_energy_conserved_over_steps():
+    esdg = _esdg()
+    spec = W.MeshSpec(4, (4, 3, 3), (0, 0, 0), (1000.0, 1000.0, 1000.0), (1, 1, 0),
+                      coriolis_f=1e-4, warp=WARP)
+    om = _oracle_mesh(spec)
+    q = torch.from_numpy(_with_jumps(W.state_iso_pert(om.coords(), spec, seed=12), 12)).cuda()
+    m = esdg.Mesh(spec)
+    dq = torch.zeros_like(q)
+    dt = m.cfl_dt(q, 0.5)
+    e0 = m.entropy(q)
+    q_start = q.clone()
+    m.lsrk_run(q, dq, dt, 50)
+    e1 = m.entropy(q)
+    moved = (q - q_start).abs().max().item()
+    assert moved > 1e-6 * q_start.abs().max().item()
+    print(f"[curved conservation] moved {moved:.3e} mass {abs(e1[1]-e0[1])/e0[1]:.2e} "
+          f"entropy {e1[0]-e0[0]:.3e} "
+          f"energy {abs(e1[2]-e0[2])/e0[2]:.2e}", flush=True)
+    assert e1[0] <= e0[0] + 1e-12 * abs(e0[0])
+    assert abs(e1[1] - e0[1]) <= 1e-14 * e0[1]
+    assert abs(e1[2] - e0[2]) <= 1e-14 * e0[2]
+
+
 def test_folding_warp_is_rejected():
     esdg = _esdg()
     spec = W.MeshSpec(4, (2, 2, 2), *_BOX, (1, 1, 0), warp=(0.6, 0.6, 0.6))
