@@ -257,7 +257,7 @@ __device__ __forceinline__ void line_terms_curved(const CurvedParams &C, const O
         for (int side = 0; side < 2; ++side)
             plus_state<NQ, R>(P, m, ec, side, qc[side ? NQ - 1 : 0], qp[side]);
     }
-    if (KEEP) {
+    if constexpr (KEEP) {
 #pragma unroll
         for (int t = 0; t < NQ; ++t)
 #pragma unroll
@@ -318,6 +318,21 @@ __device__ __forceinline__ void line_terms_curved(const CurvedParams &C, const O
     }
 }
 
+// Whether the z phase holds its line's states in registers for the finish
+// (HOLD) or the finish reads them again (L2 or last-level cache hits).  The
+// metric terms and phi take 8 NQ registers per lane beyond the affine
+// kernel's.  Up to N=3 the kernel fits two waves per SIMD either way and
+// holding saves the second read (1-8% faster on the warped bubble).  At N=4
+// holding costs half the occupancy (256 VGPRs plus 22 AGPRs against 242;
+// reading again is 15% faster), and from N=5 on it costs AGPR copies and, at
+// N=8, scratch spills (reading again is 6% faster at N=5 and 19% at N=8,
+// even at N=6 and N=7).
+template <int NQ>
+constexpr bool curved_holds_states()
+{
+    return NQ <= 4;
+}
+
 template <int NQ, int EPW, int MODE>
 __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
 {
@@ -369,16 +384,17 @@ __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
     // z phase and finish
     if (!act) return;
     const bool src = (P.mask & TERM_SRC) != 0;
-    double qv[NQ][5];
+    constexpr bool HOLD = curved_holds_states<NQ>();
+    double qv[HOLD ? NQ : 1][5];
     if (vol_or_face) {
-        line_terms_curved<NQ, 2, true>(C, tb, m, e, ec, acc, qv);
+        line_terms_curved<NQ, 2, HOLD>(C, tb, m, e, ec, acc, qv);
     } else {
 #pragma unroll
         for (int t = 0; t < NQ; ++t)
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 acc[t][v] = 0.0;
-                qv[t][v] = P.q_in[base0 + v * NQ3 + NQ2 * t];
+                if constexpr (HOLD) qv[t][v] = P.q_in[base0 + v * NQ3 + NQ2 * t];
             }
     }
     const bool use_dq = P.A != 0.0;
@@ -393,13 +409,21 @@ __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
         const int n = m + NQ2 * t;
+        double qn[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            if constexpr (HOLD)
+                qn[v] = qv[t][v];
+            else
+                qn[v] = P.q_in[base0 + v * NQ3 + NQ2 * t];
+        }
         const double iJ = C.iJ[e * NQ3 + n];
         double Rv[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] = (sacc[v][el][n] + acc[t][v]) * iJ;
         if (src) {
-            Rv[1] += P.cor_f * qv[t][2];
-            Rv[2] -= P.cor_f * qv[t][1];
+            Rv[1] += P.cor_f * qn[2];
+            Rv[2] -= P.cor_f * qn[1];
         }
         if (MODE == MODE_RHS) {
 #pragma unroll
@@ -409,13 +433,13 @@ __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
             for (int v = 0; v < 5; ++v) {
                 const double d = use_dq ? P.A * dv[t][v] + P.dt * Rv[v] : P.dt * Rv[v];
                 P.dq[base0 + v * NQ3 + NQ2 * t] = d;
-                P.q_out[base0 + v * NQ3 + NQ2 * t] = qv[t][v] + P.B * d;
+                P.q_out[base0 + v * NQ3 + NQ2 * t] = qn[v] + P.B * d;
             }
         }
         if (P.flag) {
-            const double r = qv[t][0];
-            const double kin = qv[t][1] * qv[t][1] + qv[t][2] * qv[t][2] + qv[t][3] * qv[t][3];
-            const double eint = qv[t][4] - 0.5 * kin / r - r * C.phi[e * NQ3 + n];
+            const double r = qn[0];
+            const double kin = qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3];
+            const double eint = qn[4] - 0.5 * kin / r - r * C.phi[e * NQ3 + n];
             bad |= !(r > 0.0) || !(eint > 0.0);
         }
     }
