@@ -632,6 +632,17 @@ constexpr int block_threads()
     return ((EPW * NQ * NQ + 63) / 64) * 64;
 }
 
+// Whether the z phase holds its line's states in registers for the finish.
+// At N=5 holding them costs half the occupancy (256 VGPRs plus 18 AGPRs
+// against 226 when the finish reads them again: 2.5-16% faster steps); at
+// N=6-8 reading them again does not reach two waves and was slower, and up
+// to N=4 the kernel fits two waves either way.
+template <int NQ>
+constexpr bool stage_holds_states()
+{
+    return NQ != 6;
+}
+
 // One workgroup handles EPW elements (logical block lb of the mesh); lane
 // (el, m) owns line m of element el in each of the three phases.  LDS holds
 // only the cross-phase accumulator.
@@ -709,20 +720,28 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     // z phase: lane m = (i, j) owns the nodes (i, j, 0..N) and finishes them
     if (!act) return;
     const bool src = (P.mask & TERM_SRC) != 0;
-    // the z line's states stay in registers for the update
-    double qv[NQ][5];
+    // the z line's states stay in registers for the update (HOLD), or the
+    // finish reads them again
+    constexpr bool HOLD = stage_holds_states<NQ>();
+    const double *__restrict__ qin = P.q_in;
+    double qv[HOLD ? NQ : 1][5];
     if (vol_or_face) {
-        line_terms<NQ, 2, true>(P, tb, m, e, ec, phi_k, acc, qv);
+        line_terms<NQ, 2, HOLD>(P, tb, m, e, ec, phi_k, acc, qv);
     } else {
-        const double *__restrict__ qin = P.q_in;
 #pragma unroll
         for (int t = 0; t < NQ; ++t)
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 acc[t][v] = 0.0;
-                qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
+                if constexpr (HOLD) qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
             }
     }
+    auto qs = [&](int t, int v) -> double {
+        if constexpr (HOLD)
+            return qv[t][v];
+        else
+            return qin[base0 + v * NQ3 + NQ2 * t];
+    };
     // finish.  The state arrays never overlap (checked on the host), so the
     // dq loads are issued before the first store.
     if (MODE == MODE_RHS) {
@@ -734,8 +753,8 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
 #pragma unroll
             for (int v = 0; v < 5; ++v) Rv[v] = sacc[v][el][n] + P.two_h[2] * acc[t][v];
             if (src) {
-                Rv[1] += P.cor_f * qv[t][2];
-                Rv[2] -= P.cor_f * qv[t][1];
+                Rv[1] += P.cor_f * qs(t, 2);
+                Rv[2] -= P.cor_f * qs(t, 1);
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) store_f64<true>(&rout[base0 + v * NQ3 + NQ2 * t], Rv[v]);
@@ -760,14 +779,14 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
 #pragma unroll
             for (int v = 0; v < 5; ++v) Rv[v] = sacc[v][el][n] + P.two_h[2] * acc[t][v];
             if (src) {
-                Rv[1] += P.cor_f * qv[t][2];
-                Rv[2] -= P.cor_f * qv[t][1];
+                Rv[1] += P.cor_f * qs(t, 2);
+                Rv[2] -= P.cor_f * qs(t, 1);
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 const double d = use_dq ? P.A * dv[t][v] + P.dt * Rv[v] : P.dt * Rv[v];
                 store_f64<nts>(&dqp[base0 + v * NQ3 + NQ2 * t], d);
-                store_f64<nts>(&qout[base0 + v * NQ3 + NQ2 * t], qv[t][v] + P.B * d);
+                store_f64<nts>(&qout[base0 + v * NQ3 + NQ2 * t], qs(t, v) + P.B * d);
             }
         }
     }
@@ -775,9 +794,10 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
         bool bad = false;
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
-            const double r = qv[t][0];
-            const double kin = qv[t][1] * qv[t][1] + qv[t][2] * qv[t][2] + qv[t][3] * qv[t][3];
-            const double eint = qv[t][4] - 0.5 * kin / r - r * phi_k[t];
+            const double q0 = qs(t, 0), q1 = qs(t, 1), q2 = qs(t, 2), q3 = qs(t, 3);
+            const double r = q0;
+            const double kin = q1 * q1 + q2 * q2 + q3 * q3;
+            const double eint = qs(t, 4) - 0.5 * kin / r - r * phi_k[t];
             bad |= !(r > 0.0) || !(eint > 0.0);
         }
         if (bad) atomicOr(P.flag, 1);
