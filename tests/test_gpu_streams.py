@@ -84,3 +84,29 @@ def test_nonphysical_state_is_reported_on_a_curved_mesh():
     with pytest.raises(esdg.NonPhysicalState):
         m.check()
     m.check()
+
+
+# orders where the finish reads the z-line states again instead of holding
+# them (affine N=5, curved from N=4) and one where it holds them
+@pytest.mark.parametrize("N,warp", [(5, None), (4, WARP), (6, WARP), (3, WARP)],
+                         ids=["affine_N5", "curved_N4", "curved_N6", "curved_N3"])
+def test_nonphysical_state_is_reported_by_rhs_and_stage(N, warp):
+    esdg = _esdg()
+    spec = W.MeshSpec(N, (2, 2, 2), (0, 0, 0), (900.0, 700.0, 1100.0), (1, 1, 0), warp=warp)
+    m, q, dt = _setup(spec, 2)
+    nq3 = (N + 1) ** 3
+    # a node in the last z layer of its element: the last node of a z line
+    node = nq3 - 2
+    for kind in ("rhs", "stage"):
+        qb = q.clone()
+        qb[3, 0, node] = -1.0
+        if kind == "rhs":
+            m.rhs(qb)
+        else:
+            m.lsrk_run(qb, torch.zeros_like(qb), dt, 1)
+        with pytest.raises(esdg.NonPhysicalState):
+            m.check()
+        m.check()  # flag cleared
+    # the unmodified state passes
+    m.rhs(q)
+    m.check()
