@@ -59,7 +59,7 @@ enum { ESDG_TERM_VOL = 1, ESDG_TERM_FACE = 2, ESDG_TERM_SRC = 4, ESDG_TERM_ALL =
 
 typedef struct esdg_mesh *esdg_mesh_t;
 
-/* Mesh description (paper Sec. 3 and Sec. 6 test-case geometry).
+/* Mesh description (paper Sec. 3 and the test-case geometry of Sec. 5).
  *   N            polynomial order, 1..8 (Nq = N+1 nodes per direction)
  *   K[3]         elements per direction
  *   lo/hi[3]     box corners in metres
@@ -157,7 +157,7 @@ int esdg_lsrk_step(esdg_mesh_t mesh, double *q_dev, double *dq_dev, double t, do
 int esdg_lsrk_run(esdg_mesh_t mesh, double *q_dev, double *dq_dev, double t0, double dt,
                   int32_t nsteps);
 
-/* Diagnostics (paper Sec. 6.2 tracks mass and total energy):
+/* Diagnostics (paper Sec. 5.2 tracks mass and total energy):
  * out[0] = sum_K int eta dV (eta = -rho s/(gamma-1), s = ln p - gamma ln rho),
  * out[1] = sum_K int rho dV, out[2] = sum_K int rho*E dV,
  * out[3] = sum_a J w_a v_a . R_a(q) (discrete entropy production),
@@ -183,7 +183,9 @@ int esdg_copy(const double *src, double *dst, int64_t n, void *hip_stream);
 /* Thread-local text of the last error in this thread ("" if none). */
 const char *esdg_last_error(void);
 
-/* Library version string. */
+/* Library version string, "esdg-gfx950 <version> src:<hash>", where <hash>
+ * identifies the sources the library was built from (the first 16 hex
+ * digits of a SHA-256 over the HIP sources and this header). */
 const char *esdg_version(void);
 
 /* Host-only: the library's LGL nodes xi[N+1], weights w[N+1] and
@@ -230,6 +232,14 @@ int esdg_pack_set_members(esdg_pack_t pack, int32_t n, const esdg_mesh_t *meshes
 
 /* nsteps LSRK(5,4) steps of every member (graph replay, asynchronous). */
 int esdg_pack_step(esdg_pack_t pack, int32_t nsteps);
+
+/* Failure isolation for ensemble serving: out[i] = 1 if member i (in the
+ * order of the last esdg_pack_set_members) met rho <= 0, p <= 0 or NaN in
+ * a stage since its flag was last read, else 0; the flags are cleared.  Each
+ * member's flag is its mesh's own (also read by esdg_check).  Synchronises
+ * the pack's stream; out is host memory of at least n int32.  The other
+ * members' states are unaffected by a failing one (members share no data). */
+int esdg_pack_flags(esdg_pack_t pack, int32_t *out);
 
 #ifdef __cplusplus
 }

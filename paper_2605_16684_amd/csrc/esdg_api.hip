@@ -659,7 +659,11 @@ extern "C" {
 
 const char *esdg_last_error(void) { return g_err.c_str(); }
 
-const char *esdg_version(void) { return "esdg-gfx950 0.1"; }
+#ifndef ESDG_SOURCE_HASH
+#define ESDG_SOURCE_HASH "unknown"
+#endif
+
+const char *esdg_version(void) { return "esdg-gfx950 0.2 src:" ESDG_SOURCE_HASH; }
 
 int esdg_lgl_tables(int32_t N, double *xi, double *w, double *D)
 {
@@ -1028,6 +1032,9 @@ struct esdg_pack {
     int n, N, precision, epw, nblocks, capacity;
     void *d_members;     // PackMember[] or PackMemberMixed[]
     int *d_parity;
+    int **d_flagptrs;    // each member mesh's non-physical flag
+    int *d_flags;        // gathered flags
+    int *h_flags;        // pinned copy of d_flags
     hipGraphExec_t graph;
 };
 
@@ -1132,6 +1139,9 @@ int esdg_pack_destroy(esdg_pack_t p)
     pack_drop_graph(p);
     if (p->d_members) (void)hipFree(p->d_members);
     if (p->d_parity) (void)hipFree(p->d_parity);
+    if (p->d_flagptrs) (void)hipFree(p->d_flagptrs);
+    if (p->d_flags) (void)hipFree(p->d_flags);
+    if (p->h_flags) (void)hipHostFree(p->h_flags);
     delete p;
     return rc;
 }
@@ -1149,6 +1159,7 @@ int esdg_pack_set_members(esdg_pack_t p, int32_t n, const esdg_mesh_t *meshes, d
     int64_t blocks = 0;
     const bool mixed = prec == ESDG_FP32_MIXED;
     std::string tab(mixed ? sizeof(PackMemberMixed) * n : sizeof(PackMember) * n, '\0');
+    std::vector<int *> flagptrs(n);
     for (int i = 0; i < n; ++i) {
         esdg_mesh *m = meshes[i];
         if (!m) return fail(ESDG_EINVAL, "member %d: NULL mesh", i);
@@ -1169,6 +1180,7 @@ int esdg_pack_set_members(esdg_pack_t p, int32_t n, const esdg_mesh_t *meshes, d
         P.dq = dq[i];
         P.dt = dt[i];
         P.nblocks = (int)((m->ne + epw - 1) / epw);
+        flagptrs[i] = m->d_flag;
         if (mixed) {
             PackMemberMixed pm;
             std::memset(&pm, 0, sizeof pm);
@@ -1199,22 +1211,48 @@ int esdg_pack_set_members(esdg_pack_t p, int32_t n, const esdg_mesh_t *meshes, d
     HIP_TRY(hipStreamSynchronize(p->stream));
     pack_drop_graph(p);
     if (n > p->capacity) {
+        // grow geometrically; the new tables are allocated before the old
+        // ones are freed, so a failed allocation leaves the pack as it was
+        const int cap = std::max(n, 2 * p->capacity);
+        void *members = nullptr;
+        int *par = nullptr, *flags = nullptr, *hflags = nullptr;
+        int **fptrs = nullptr;
+        const bool ok =
+            hipMalloc(&members, std::max(sizeof(PackMember), sizeof(PackMemberMixed)) * cap) ==
+                hipSuccess &&
+            hipMalloc(&par, sizeof(int) * cap) == hipSuccess &&
+            hipMalloc(&fptrs, sizeof(int *) * cap) == hipSuccess &&
+            hipMalloc(&flags, sizeof(int) * cap) == hipSuccess &&
+            hipHostMalloc(&hflags, sizeof(int) * cap, hipHostMallocDefault) == hipSuccess;
+        if (!ok) {
+            if (members) (void)hipFree(members);
+            if (par) (void)hipFree(par);
+            if (fptrs) (void)hipFree(fptrs);
+            if (flags) (void)hipFree(flags);
+            if (hflags) (void)hipHostFree(hflags);
+            return fail(ESDG_ENOMEM, "pack table allocation failed");
+        }
         if (p->d_members) (void)hipFree(p->d_members);
         if (p->d_parity) (void)hipFree(p->d_parity);
-        p->d_members = nullptr;
-        p->d_parity = nullptr;
-        p->capacity = 0;
-        const int cap = std::max(n, 2 * p->capacity);
-        if (hipMalloc(&p->d_members, std::max(sizeof(PackMember), sizeof(PackMemberMixed)) * cap) !=
-                hipSuccess ||
-            hipMalloc(&p->d_parity, sizeof(int) * cap) != hipSuccess)
-            return fail(ESDG_ENOMEM, "pack table allocation failed");
+        if (p->d_flagptrs) (void)hipFree(p->d_flagptrs);
+        if (p->d_flags) (void)hipFree(p->d_flags);
+        if (p->h_flags) (void)hipHostFree(p->h_flags);
+        p->d_members = members;
+        p->d_parity = par;
+        p->d_flagptrs = fptrs;
+        p->d_flags = flags;
+        p->h_flags = hflags;
         p->capacity = cap;
     }
+    // from here on the device table no longer matches the old member set:
+    // a failed upload leaves an empty pack, whose step() is rejected
+    p->n = 0;
     HIP_TRY(hipMemcpyAsync(p->d_members, tab.data(), tab.size(), hipMemcpyHostToDevice,
                            p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_parity, parity, sizeof(int32_t) * n, hipMemcpyHostToDevice,
                            p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_flagptrs, flagptrs.data(), sizeof(int *) * n,
+                           hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->n = n;
     p->N = N;
@@ -1256,6 +1294,24 @@ int esdg_pack_step(esdg_pack_t p, int32_t nsteps)
         }
     }
     for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(p->graph, p->stream));
+    return ESDG_OK;
+}
+
+int esdg_pack_flags(esdg_pack_t p, int32_t *out)
+{
+    if (!p) return fail(ESDG_EINVAL, "NULL pack");
+    if (!out) return fail(ESDG_EINVAL, "out is NULL");
+    if (p->n < 1) return fail(ESDG_EINVAL, "pack has no members");
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) HIP_TRY(hipSetDevice(p->device));
+    hipLaunchKernelGGL(pack_flags_kernel, dim3((unsigned)((p->n + 255) / 256)), dim3(256), 0,
+                       p->stream, (int *const *)p->d_flagptrs, p->n, p->d_flags);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(p->h_flags, p->d_flags, sizeof(int) * p->n, hipMemcpyDeviceToHost,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    for (int i = 0; i < p->n; ++i) out[i] = p->h_flags[i] ? 1 : 0;
     return ESDG_OK;
 }
 

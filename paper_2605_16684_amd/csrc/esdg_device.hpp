@@ -865,6 +865,17 @@ __global__ void pack_flip_kernel(int *parity, int n)
     if (i < n) parity[i] ^= 1;
 }
 
+// Gathers every member's non-physical flag into out[i] and clears it.
+__global__ void pack_flags_kernel(int *const *flags, int n, int *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        int *f = flags[i];
+        out[i] = *f;
+        *f = 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Auxiliary kernels: node coordinates, diagnostics, time-step bound.
 // ---------------------------------------------------------------------------

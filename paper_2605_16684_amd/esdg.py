@@ -84,6 +84,7 @@ SIGNATURES = {
                                         C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                         C.POINTER(C.c_void_p), _dp, C.POINTER(C.c_int32)]),
     "esdg_pack_step": (C.c_int, [C.c_void_p, C.c_int32]),
+    "esdg_pack_flags": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
 }
 
 
@@ -96,6 +97,15 @@ def _load():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
+    # refuse a library built from other sources than the ones in this tree
+    from . import build as _build
+    version = lib.esdg_version().decode()
+    want = _build.source_hash()
+    have = version.rsplit("src:", 1)[-1] if "src:" in version else "none"
+    if have != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (library {have}, "
+                          f"tree {want}): rebuild it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
     return lib
 
 
@@ -313,3 +323,11 @@ class Pack:
 
     def step(self, nsteps: int = 1):
         _check(lib.esdg_pack_step(self._h, nsteps))
+
+    def flags(self):
+        """Per member (in set_members order): True if it met a non-physical
+        state since the last read (the flags are cleared).  Synchronises the
+        pack's stream."""
+        buf = (C.c_int32 * max(self.n, 1))()
+        _check(lib.esdg_pack_flags(self._h, buf))
+        return [bool(buf[i]) for i in range(self.n)]

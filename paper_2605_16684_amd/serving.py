@@ -43,6 +43,10 @@ from . import workloads as W
 FP64, FP32_MIXED = 0, 1
 
 
+class NonPhysicalState(RuntimeError):
+    """A member met rho <= 0, p <= 0 or NaN; it was evicted, the others run on."""
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
@@ -53,6 +57,9 @@ class Request:
     seed: int
     steps: int
     arrival: float = 0.0       # seconds after the start of the run
+    # failure-isolation tests: write a negative density at this node index
+    # (element 0, flat node index) of the initial state
+    nonphysical_node: Optional[int] = None
 
     def spec(self) -> W.MeshSpec:
         if self.kind == "bubble":
@@ -180,6 +187,8 @@ def _make_member_mesh(req: Request, epw: int = 0):
         m = esdg.Mesh(spec, epw=epw)
         xyz = m.coords()
     q = W.make_state(req.kind, xyz, spec, seed=req.seed).contiguous()
+    if req.nonphysical_node is not None:
+        q[0, 0, req.nonphysical_node] = -1.0
     return m, q, xyz
 
 
@@ -197,6 +206,7 @@ class Member:
     steps_done: int = 0
     latencies: List[float] = dataclasses.field(default_factory=list)
     finished: float = 0.0
+    error: Optional[Exception] = None  # set when the member was evicted
 
 
 class GpuExecutor:
@@ -212,6 +222,9 @@ class GpuExecutor:
         self.ev0 = torch.cuda.Event(enable_timing=True)
         self.ev0.record()
         torch.cuda.synchronize()
+        # host seconds spent per activity, and device seconds of the steps
+        self.times = {"admission_s": 0.0, "set_members_s": 0.0, "launch_and_capture_s": 0.0,
+                      "flag_reads_s": 0.0, "release_s": 0.0, "device_step_s": 0.0}
 
     def now(self) -> float:
         return time.perf_counter() - self.t0_host
@@ -221,20 +234,28 @@ class GpuExecutor:
 
     def admit(self, req: Request):
         torch = self.torch
+        t0 = time.perf_counter()
         epw = self.autotuner.epw(req.N, req.precision)
         m, q, xyz = _make_member_mesh(req, epw=epw)
         del xyz
-        dt = m.cfl_dt(q, 0.5)
+        try:
+            dt = m.cfl_dt(q, 0.5)
+        except Exception:
+            # a state without a finite wave speed still enters and is evicted
+            # by its flag after its first step; its time step is immaterial
+            dt = 1e-3
         q1 = torch.empty_like(q)
         dq = torch.zeros_like(q)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         ev.synchronize()
+        self.times["admission_s"] += time.perf_counter() - t0
         return {"mesh": m, "bufs": [q, q1], "dq": dq, "dt": dt, "parity": 0}, self._dev_time(ev)
 
     def set_bucket(self, key, members: List[Member]):
         from . import esdg
         torch = self.torch
+        t0 = time.perf_counter()
         b = self.buckets.get(key)
         if b is None:
             stream = torch.cuda.Stream()
@@ -251,6 +272,7 @@ class GpuExecutor:
                                   [h["bufs"][1] for h in hs], [h["dq"] for h in hs],
                                   [h["dt"] for h in hs], [h["parity"] for h in hs])
         b["members"] = list(members)
+        self.times["set_members_s"] += time.perf_counter() - t0
 
     def drop_bucket(self, key):
         b = self.buckets.pop(key, None)
@@ -259,31 +281,54 @@ class GpuExecutor:
 
     def launch_step(self, key):
         torch = self.torch
+        t0 = time.perf_counter()
         b = self.buckets[key]
         with torch.cuda.stream(b["stream"]):
-            b["pack"].step(1)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev0.record(b["stream"])
+            b["pack"].step(1)  # the first step after set_members captures the graph
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(b["stream"])
         for mb in b["members"]:
             mb.handle["parity"] ^= 1
+        b["ev_start"] = ev0
+        self.times["launch_and_capture_s"] += time.perf_counter() - t0
         return ev
+
+    def failed_members(self, key) -> List[Member]:
+        """Members of the bucket's completed step whose own non-physical flag
+        is set (the flags are cleared)."""
+        t0 = time.perf_counter()
+        b = self.buckets[key]
+        if b.get("ev_start") is not None:
+            self.times["device_step_s"] += b["ev_start"].elapsed_time(b["ev_done"]) * 1e-3 \
+                if b.get("ev_done") is not None else 0.0
+        flags = b["pack"].flags()
+        self.times["flag_reads_s"] += time.perf_counter() - t0
+        return [mb for mb, f in zip(b["members"], flags) if f]
 
     def poll(self, tokens: Dict[tuple, object], until: Optional[float] = None) -> Dict[tuple, float]:
         """Device completion times of the in-flight steps that have finished;
         waits until at least one has, or until host time `until`."""
         while True:
-            out = {key: self._dev_time(ev) for key, ev in tokens.items() if ev.query()}
+            out = {}
+            for key, ev in tokens.items():
+                if ev.query():
+                    out[key] = self._dev_time(ev)
+                    self.buckets[key]["ev_done"] = ev
             if out or (until is not None and self.now() >= until):
                 return out
             time.sleep(5e-5)
 
-    def release(self, mb: Member):
+    def release(self, mb: Member, keep: bool = True):
+        t0 = time.perf_counter()
         h = mb.handle
         result = None
-        if self.keep_results:
+        if self.keep_results and keep:
             result = h["bufs"][h["parity"]].cpu().numpy()
         h["mesh"].close()
         mb.handle = None
+        self.times["release_s"] += time.perf_counter() - t0
         return result
 
 
@@ -293,7 +338,8 @@ class FakeExecutor:
     share the device equally (processor sharing, as concurrent streams share
     the CUs).  Time is virtual."""
 
-    def __init__(self, cost_per_node=None, overhead=20e-6, admit_cost=1e-3, fail_on=None):
+    def __init__(self, cost_per_node=None, overhead=20e-6, admit_cost=1e-3, fail_on=None,
+                 nonphysical_on=None):
         self.cost = cost_per_node or (lambda N, prec: 5 * 1e-10 * (1.0 if prec == FP64 else 0.8))
         self.overhead = overhead
         self.admit_cost = admit_cost
@@ -302,6 +348,9 @@ class FakeExecutor:
         self.finished: Dict[tuple, float] = {}  # bucket -> completion time
         self.buckets: Dict[tuple, List[Member]] = {}
         self.fail_on = fail_on or set()
+        # request id -> step (1-based) after which its flag reads non-physical
+        self.nonphysical_on = dict(nonphysical_on or {})
+        self.times = {}
 
     def now(self) -> float:
         return self.clock
@@ -358,7 +407,12 @@ class FakeExecutor:
                 return {k: self.finished.pop(k) for k in list(tokens) if k in self.finished}
             self._run_until(t_next)
 
-    def release(self, mb):
+    def failed_members(self, key):
+        return [mb for mb in self.buckets.get(key, [])
+                if mb.req.rid in self.nonphysical_on
+                and mb.steps_done + 1 >= self.nonphysical_on[mb.req.rid]]
+
+    def release(self, mb, keep: bool = True):
         return None
 
 
@@ -383,6 +437,8 @@ class RunStats:
     bucket_steps: int
     max_concurrent_members: int
     buckets_seen: int
+    n_failed: int = 0
+    time_breakdown: Optional[dict] = None
 
     def as_dict(self):
         return dataclasses.asdict(self)
@@ -398,19 +454,30 @@ class RequestHandle:
         self.req = req
 
     def done(self) -> bool:
+        """True once the request has completed or failed."""
         mb = self._server.members.get(self.req.rid)
-        return mb is not None and mb.steps_done >= self.req.steps
+        return mb is not None and (mb.steps_done >= self.req.steps or mb.error is not None)
+
+    def error(self) -> Optional[Exception]:
+        """The error that evicted the request (e.g. NonPhysicalState), or None."""
+        mb = self._server.members.get(self.req.rid)
+        return None if mb is None else mb.error
 
     def result(self):
         if not self.done():
             raise RuntimeError(f"request {self.req.rid} has not completed "
                                "(call Server.run_until_idle)")
+        err = self.error()
+        if err is not None:
+            raise err
         return self._server.results.get(self.req.rid)
 
     def stats(self) -> dict:
         if not self.done():
             raise RuntimeError(f"request {self.req.rid} has not completed")
         mb = self._server.members[self.req.rid]
+        if mb.error is not None:
+            raise mb.error
         lat = np.array(mb.latencies)
         return {"steps": mb.steps_done, "queue_wait_s": mb.admitted - self.req.arrival,
                 "e2e_latency_s": mb.finished - self.req.arrival,
@@ -458,6 +525,7 @@ class Server:
         used = peak = 0
         rejected = 0
         done: List[Member] = []
+        failed: List[Member] = []
         steps_launched = max_conc = 0
         buckets_seen = set()
         inflight: Dict[tuple, object] = {}      # bucket -> completion token of its step
@@ -523,7 +591,23 @@ class Server:
             until = t_start + pending[0].arrival if pending else None
             for key, t_end in ex.poll(inflight, until).items():
                 del inflight[key]
+                # failure isolation: a member whose own flag reports a
+                # non-physical state is evicted with an error; the others
+                # (which share no data with it) carry on
+                bad = {id(mb) for mb in ex.failed_members(key)}
                 for mb in stepping.pop(key):
+                    if id(mb) in bad:
+                        mb.error = NonPhysicalState(
+                            f"request {mb.req.rid}: non-physical state (rho <= 0, p <= 0 or "
+                            f"NaN) in step {mb.steps_done + 1}")
+                        mb.finished = ex.now() - t_start
+                        ex.release(mb, keep=False)
+                        mb.handle = None
+                        active[key].remove(mb)
+                        used -= mb.footprint
+                        failed.append(mb)
+                        dirty.add(key)
+                        continue
                     mb.latencies.append(t_end - mb.last_done)
                     mb.last_done = t_end
                     mb.steps_done += 1
@@ -552,5 +636,6 @@ class Server:
             queue_wait_p99_ms=float(np.percentile(waits, 99) * 1e3),
             e2e_latency_mean_s=float(e2e.mean()), peak_footprint_bytes=int(peak),
             hbm_budget_bytes=self.budget, bucket_steps=steps_launched, max_concurrent_members=max_conc,
-            buckets_seen=len(buckets_seen))
+            buckets_seen=len(buckets_seen), n_failed=len(failed),
+            time_breakdown=dict(getattr(ex, "times", {}) or {}) or None)
         return self._last

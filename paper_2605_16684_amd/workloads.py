@@ -8,7 +8,7 @@ returned in the boundary layout q[e][v][n] with v in (rho, rho u, rho v,
 rho w, rho E) and E = p/(gamma-1) + rho |u|^2 / 2 + rho g z, the total energy
 with geopotential of the governing equations (Sec. 2 of the paper).
 
-The shapes follow the paper's test cases (Sec. 6): a rising thermal bubble
+The shapes follow the paper's test cases (Sec. 5): a rising thermal bubble
 in a neutral atmosphere (smooth cosine perturbation of potential
 temperature) and a zonal-jet channel in hydrostatic, geostrophically
 balanced background with a Gaussian wind perturbation.  The paper's channel
@@ -175,7 +175,7 @@ def state_iso_rest(xyz, spec: MeshSpec, T=300.0):
 def state_bubble(xyz, spec: MeshSpec, seed: Optional[int] = None, theta0=300.0, amp=0.5,
                  rc=250.0, centre=(500.0, 500.0, 350.0)):
     """Neutral atmosphere with the smooth cosine bubble
-    dtheta = amp (1 + cos(pi r/rc))/2 for r <= rc (Sec. 6.1); p is the
+    dtheta = amp (1 + cos(pi r/rc))/2 for r <= rc (Sec. 5.1); p is the
     background hydrostatic pressure, u = 0.  A seed jitters the centre
     (+-50 m) and the amplitude (x [0.8, 1.2])."""
     if seed is not None:

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_2605_16684_amd import workloads as W
-from tests._parity import TOL_RHS, TOL_STATE, err_gross, err_net, kappa
+from tests._parity import check_rhs, check_state, err_gross
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -67,11 +67,7 @@ def test_curved_rhs_parity(name, N, K, periodic, f, surf, state):
     m = esdg.Mesh(spec)
     r = m.rhs(torch.from_numpy(q).cuda()).cpu().numpy()
     m.check()
-    eg, en, k = err_gross(r, r_or, g), err_net(r, r_or), kappa(r_or, g)
-    print(f"[curved {name}] err/gross={np.array2string(eg, precision=2)} "
-          f"err/net={np.array2string(en, precision=2)} kappa={np.array2string(k, precision=1)}",
-          flush=True)
-    assert np.all(eg <= TOL_RHS), eg
+    check_rhs(f"curved {name}", r, r_or, g)
 
 
 def test_curved_node_coords_diagnostics_and_cfl_match_oracle():
@@ -114,14 +110,12 @@ def test_curved_lsrk_100_steps_parity(surf):
     q0 = W.state_iso_pert(om.coords(), spec, seed=1)
     dt = om.cfl_dt(q0, 0.5)
     q_or = om.run(q0, dt, 100)
+    _, g0 = om.rhs(q0, gross=True)
     m = esdg.Mesh(spec)
     qg = torch.from_numpy(q0).cuda()
     dq = torch.zeros_like(qg)
     m.lsrk_run(qg, dq, dt, 100)
-    e = err_net(qg.cpu().numpy(), q_or)
-    print(f"[curved lsrk100 surf={surf}] state rel L2 per var {np.array2string(e, precision=2)}",
-          flush=True)
-    assert np.all(e <= TOL_STATE), e
+    check_state(f"curved lsrk100 surf={surf}", qg.cpu().numpy(), q_or, g0, 100 * dt, 100)
     # eager steps give the graph's bits
     qe = torch.from_numpy(q0).cuda()
     dqe = torch.zeros_like(qe)
@@ -198,9 +192,7 @@ def test_curved_term_split_parity(mask):
     _, g = om.rhs(q, gross=True)
     m = esdg.Mesh(spec)
     r = m.rhs_terms(torch.from_numpy(q).cuda(), mask).cpu().numpy()
-    eg = err_gross(r, r_or, g)
-    print(f"[curved mask {mask}] err/gross={np.array2string(eg, precision=2)}", flush=True)
-    assert np.all(eg <= TOL_RHS), eg
+    check_rhs(f"curved mask {mask}", r, r_or, g)
 
 
 def test_curved_mesh_is_not_packed():

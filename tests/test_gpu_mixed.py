@@ -1,17 +1,15 @@
 """FP32-mixed path against the FP64 oracle.
 
-Bars (stated per result): RHS error relative to the gross term scale
-<= 1e-5 per conserved variable; state after 100 LSRK(5,4) steps within
-1e-4 relative L2 per conserved quantity (density, the momentum vector,
-total energy; the Cartesian momentum components are printed too, but a
-near-zero component such as the vertical momentum of a zonal jet has no
-meaningful relative error of its own); mass and total-energy drift within
-1e-10 (FP32 fluxes conserve to their own rounding; the paper reports ~1e-7
-for its FP32 runs); entropy drift reported.  The net relative
-RHS error is printed beside the bar, and for the buoyancy-carrying vertical
-momentum of a perturbed hydrostatic state it is bounded too (the reference
-subtraction keeps it at the FP32 level of the perturbation, not of the full
-pressure).
+Bars (stated per result, tests/_parity.py): per conserved variable, the RHS
+error is at most 1e-5 of the gross term scale and at most
+max(1e-5, eps32 kappa_v) of the RHS itself (one FP32 rounding of the gross
+terms: where the RHS is a small residual of large terms, as for the
+channel's density and energy, no FP32 evaluation of those terms can do
+better); the state after 100 LSRK(5,4) steps is within
+max(1e-4, eps32 kappa_s / sqrt(500)) relative L2 per Cartesian component;
+mass and total-energy drift within 1e-10 (FP32 fluxes conserve to their own
+rounding; the paper reports ~1e-7 for its FP32 runs); entropy drift
+reported beside the oracle's.
 """
 from dataclasses import replace
 
@@ -20,13 +18,10 @@ import pytest
 
 import oracle as O
 from paper_2605_16684_amd import workloads as W
-from tests._parity import err_gross, err_net, kappa
+from tests._parity import check_rhs, check_state, err_gross
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
-
-TOL_RHS_MIXED = 1e-5
-TOL_STATE_MIXED = 1e-4
 
 
 def _esdg():
@@ -85,16 +80,7 @@ def test_mixed_rhs_error(name, spec, kind):
     r_or, g = om.rhs(q, gross=True)
     m = _mixed_mesh(spec, xyz, kind)
     r = m.rhs(torch.from_numpy(q).cuda()).cpu().numpy()
-    eg, en, k = err_gross(r, r_or, g), err_net(r, r_or), kappa(r_or, g)
-    print(f"[mixed {name}] err/gross={np.array2string(eg, precision=2)} "
-          f"err/net={np.array2string(en, precision=2)} kappa={np.array2string(k, precision=1)}",
-          flush=True)
-    assert np.all(eg <= TOL_RHS_MIXED), eg
-    # vertical momentum: the reference subtraction keeps the error at the
-    # FP32 level of the perturbation terms (full-variable FP32 would leave
-    # ~1e-8 of the hydrostatic pressure terms, i.e. err/net ~ eps32 * kappa)
-    if k[3] < 1e8:
-        assert en[3] <= max(1e-5, 50 * 6e-8 * k[3] * 1e-3), en[3]
+    check_rhs(f"mixed {name}", r, r_or, g, mixed=True)
 
 
 def _with_jumps(q, seed):
@@ -125,10 +111,7 @@ def test_mixed_rhs_error_matrix_dissipation(name, spec, kind, jumps):
     r_or, g = om.rhs(q, gross=True)
     m = _mixed_mesh(spec, xyz, kind)
     r = m.rhs(torch.from_numpy(q).cuda()).cpu().numpy()
-    eg, en = err_gross(r, r_or, g), err_net(r, r_or)
-    print(f"[mixed {name} jumps={jumps}] err/gross={np.array2string(eg, precision=2)} "
-          f"err/net={np.array2string(en, precision=2)}", flush=True)
-    assert np.all(eg <= TOL_RHS_MIXED), eg
+    check_rhs(f"mixed {name} jumps={jumps}", r, r_or, g, mixed=True)
 
 
 def test_mixed_full_size_sampled_channel_N7():
@@ -147,9 +130,8 @@ def test_mixed_full_size_sampled_channel_N7():
     rng = np.random.default_rng(0)
     el = np.unique(np.concatenate([rng.choice(om.ne, 32, replace=False), [0, om.ne - 1]]))
     r_or, g = om.rhs_elems(q, el)
-    eg = err_gross(r[el], r_or, g)
-    print(f"[mixed c3-sampled] err/gross={np.array2string(eg, precision=2)} epw={m.epw}", flush=True)
-    assert np.all(eg <= TOL_RHS_MIXED), eg
+    print(f"[mixed c3-sampled] epw={m.epw}", flush=True)
+    check_rhs("mixed c3-sampled", r[el], r_or, g, mixed=True)
     m.close()
 
 
@@ -177,6 +159,7 @@ def test_mixed_100_steps_against_oracle(name, wl):
     q0 = W.make_state(wl.kind, xyz, spec, seed=3)
     dt = om.cfl_dt(q0, wl.cfl)
     q_or = om.run(q0, dt, 100)
+    _, g0 = om.rhs(q0, gross=True)
     m = _mixed_mesh(spec, xyz, wl.kind)
     q = torch.from_numpy(q0).cuda()
     dq = torch.zeros_like(q)
@@ -185,16 +168,10 @@ def test_mixed_100_steps_against_oracle(name, wl):
     e1 = m.entropy(q)
     eo0, eo1 = om.entropy(q0), om.entropy(q_or)
     qa = q.cpu().numpy()
-    e = err_net(qa, q_or)
-    d = qa - q_or
-    eq = np.array([np.linalg.norm(d[:, 0]) / np.linalg.norm(q_or[:, 0]),
-                   np.linalg.norm(d[:, 1:4]) / np.linalg.norm(q_or[:, 1:4]),
-                   np.linalg.norm(d[:, 4]) / np.linalg.norm(q_or[:, 4])])
-    print(f"[mixed 100 steps {name}] state rel L2 (rho, m, E) {np.array2string(eq, precision=2)} "
-          f"per component {np.array2string(e, precision=2)}; "
+    print(f"[mixed 100 steps {name}] "
           f"entropy change mixed {(e1[0]-e0[0])/abs(e0[0]):.3e} oracle {(eo1[0]-eo0[0])/abs(eo0[0]):.3e}; "
           f"mass drift {abs(e1[1]-e0[1])/e0[1]:.2e} energy drift {abs(e1[2]-e0[2])/e0[2]:.2e}",
           flush=True)
-    assert np.all(eq <= TOL_STATE_MIXED), eq
+    check_state(f"mixed 100 steps {name}", qa, q_or, g0, 100 * dt, 100, mixed=True)
     assert abs(e1[1] - e0[1]) <= 1e-10 * e0[1]
     assert abs(e1[2] - e0[2]) <= 1e-10 * e0[2]

@@ -1,6 +1,8 @@
 """Ensemble serving on the GPU: packed launches reproduce single-mesh
-stepping bit for bit, and every request's result is the same alone and in
-the mix (FP64 and FP32-mixed members; bitwise, the tolerance is 0)."""
+stepping bit for bit, every request's result is the same alone and in the
+mix (FP64 and FP32-mixed members; bitwise, the tolerance is 0), a member
+that goes non-physical is evicted alone, and the pack's member table grows
+and shrinks without changing any member's result."""
 import numpy as np
 import pytest
 
@@ -67,3 +69,63 @@ def test_autotuner_caches_a_compiled_choice(tmp_path):
     assert e in esdg.epw_options(4, S.FP64)
     t2 = S.Autotuner(str(path))
     assert t2.table["N4_fp64"]["epw"] == e
+
+
+def test_nonphysical_member_fails_alone_in_a_mix(tmp_path):
+    """One member of a mixed stream starts with a negative density at one
+    node: that request fails with NonPhysicalState, every other request ends
+    bitwise equal to its solo run."""
+    tuner = S.Autotuner(str(tmp_path / "epw.json"), target_nodes=1.5e5)
+    reqs = S.request_stream(n=6, seed=11, mean_interarrival=1e-6, steps=4, kmin=2, kmax=4,
+                            orders=(3, 4))
+    bad = reqs[2]
+    reqs[2] = S.Request(bad.rid, bad.kind, bad.K, bad.N, bad.precision, bad.seed, bad.steps,
+                        bad.arrival, nonphysical_node=7)
+    ex = S.GpuExecutor(tuner, keep_results=True)
+    srv = S.Server(10 * sum(S.footprint_bytes(r) for r in reqs), executor=ex)
+    handles = [srv.submit(r) for r in reqs]
+    st = srv.run_until_idle()
+    print("[serving nonphysical]", st.as_dict(), flush=True)
+    assert st.n_failed == 1 and st.n_completed == len(reqs) - 1
+    assert st.max_concurrent_members > 1
+    assert isinstance(handles[2].error(), S.NonPhysicalState)
+    with pytest.raises(S.NonPhysicalState):
+        handles[2].result()
+    for r, h in zip(reqs, handles):
+        if r.rid == bad.rid:
+            continue
+        alone = S.Server(10 * S.footprint_bytes(r), executor=S.GpuExecutor(tuner, keep_results=True))
+        ha = alone.submit(S.Request(r.rid, r.kind, r.K, r.N, r.precision, r.seed, r.steps, 0.0))
+        alone.run_until_idle()
+        a, b = h.result(), ha.result()
+        assert np.array_equal(a, b), (r, np.abs(a - b).max())
+        assert np.all(np.isfinite(a))
+
+
+def test_pack_table_grows_and_shrinks():
+    """Member sets of 1, 3, 2 and 5 meshes in a row (the device table grows
+    geometrically and is reused when it shrinks): every member's two steps
+    equal its single-mesh steps bit for bit, and the flags read clean."""
+    from paper_2605_16684_amd import esdg
+    reqs = [S.Request(i, "bubble" if i % 2 else "channel", (2 + i % 3, 2, 2), 3, S.FP64, i, 2)
+            for i in range(5)]
+    built = []
+    for r in reqs:
+        m, q, _ = S._make_member_mesh(r)
+        dt = m.cfl_dt(q, 0.5)
+        qa, dqa = q.clone(), torch.zeros_like(q)
+        for _ in range(2):
+            m.lsrk_step(qa, dqa, dt)
+        built.append((m, q, dt, qa))
+    pack = esdg.Pack()
+    for sel in ([0], [0, 1, 2], [3, 4], [0, 1, 2, 3, 4]):
+        bufs = [(built[i][1].clone(), torch.empty_like(built[i][1]), torch.zeros_like(built[i][1]))
+                for i in sel]
+        pack.set_members([built[i][0] for i in sel], [b[0] for b in bufs], [b[1] for b in bufs],
+                         [b[2] for b in bufs], [built[i][2] for i in sel], [0] * len(sel))
+        pack.step(2)
+        torch.cuda.synchronize()
+        assert pack.flags() == [False] * len(sel)
+        for i, b in zip(sel, bufs):
+            assert torch.equal(b[0], built[i][3]), (sel, i)   # 2 steps: back in buffer 0
+    pack.close()

@@ -3,7 +3,7 @@
 Paper: semi-discrete ES-DGSEM (Sec. 3, Eq. nm:semi, read as the
 Jacobian-weighted skew flux-differencing form), discrete entropy stability
 of the two-point flux (Sec. 3), conservation of mass and total energy to
-machine precision (Sec. 6.2), LSRK(5,4) stepping (Sec. 3).  Every check is
+machine precision (Sec. 5.2), LSRK(5,4) stepping (Sec. 3).  Every check is
 against mathematics that does not come from the oracle itself: the strong
 form written independently, exact solutions, invariants, and the entropy
 variables as the gradient of eta.

@@ -78,6 +78,26 @@ def test_failure_isolation():
     assert 3 not in srv.members
 
 
+def test_nonphysical_member_is_evicted_and_others_complete():
+    rs = _reqs(n=8, steps=6)
+    ex = S.FakeExecutor(nonphysical_on={2: 3})      # request 2 goes bad in its third step
+    srv = S.Server(10 * max(S.footprint_bytes(r) for r in rs), executor=ex)
+    handles = {r.rid: S.RequestHandle(srv, r) for r in rs}
+    st = srv.run(rs, realtime=False)
+    assert st.n_failed == 1 and st.n_completed == 7 and st.n_rejected == 0
+    h = handles[2]
+    assert h.done() and isinstance(h.error(), S.NonPhysicalState)
+    with pytest.raises(S.NonPhysicalState):
+        h.result()
+    assert srv.members[2].steps_done == 2            # evicted after its third step
+    for r in rs:
+        if r.rid != 2:
+            assert handles[r.rid].error() is None
+            assert srv.members[r.rid].steps_done == r.steps
+    # its memory returned to the budget: nothing is left resident
+    assert all(mb.handle is None or mb.error is None for mb in srv.members.values())
+
+
 def test_statistics_are_computed_from_member_steps():
     rs = _reqs(n=6, steps=4)
     srv = S.Server(10 * max(S.footprint_bytes(r) for r in rs), executor=S.FakeExecutor())
