@@ -26,9 +26,17 @@ _ip = C.POINTER(C.c_int)
 _i64p = C.POINTER(C.c_int64)
 
 
+def _stale(lib, sources):
+    return not os.path.exists(lib) or any(os.path.getmtime(lib) < os.path.getmtime(f)
+                                          for f in sources)
+
+
+_POINTWISE = os.path.join(_HERE, "esdg_pointwise.h")
+
+
 def _load():
-    if not os.path.exists(_LIB_PATH) or (
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_build.SRC)):
+    if _stale(_LIB_PATH, (_build.SRC, _POINTWISE)) or \
+            _stale(_build.OPC_LIB, (_build.OPC_SRC, _POINTWISE)):
         _build.build()
     lib = C.CDLL(_LIB_PATH)
     sig = {
@@ -76,6 +84,43 @@ def _load():
 
 
 _lib = _load()
+_opc = None
+
+# operation classes of op_count (one flop each)
+OP_CLASSES = ("add", "mul", "div", "sqrt", "log")
+OP_NODE, OP_FLUX, OP_GRAVITY, OP_SURFACE, OP_SOURCE, OP_UPDATE, OP_LOGMEAN = range(7)
+
+
+def op_count(what, r=0, qa=(1.0, 0, 0, 0, 2.5), qb=(1.0, 0, 0, 0, 2.5), phia=0.0, phib=0.0,
+             gamma=1.4, surf=SURF_RUSANOV):
+    """Operation counts of one call of the oracle's pointwise physics
+    (libopcount.so: esdg_pointwise.h compiled over a counting scalar).
+
+    what: OP_NODE (per-node quantities of qa), OP_FLUX (two-point flux
+    F_r(qa, qb)), OP_GRAVITY (its gravity term), OP_SURFACE (face flux of
+    qa, qb for the normal +e_r and surface flux `surf`), OP_SOURCE (Coriolis
+    source of qa with f = phia), OP_UPDATE (LSRK update of one value with
+    A, B, dt, R = qa[0:4] and dq, q = qb[0:2]), OP_LOGMEAN ({{qa[0], qb[0]}}_log).
+    Returns (counts, values): counts maps each of OP_CLASSES to its count,
+    values the up to five numbers the call computed."""
+    global _opc
+    if _opc is None:
+        _opc = C.CDLL(_build.OPC_LIB)
+        _opc.oracle_op_count.restype = C.c_int
+        _opc.oracle_op_count.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double,
+                                         C.c_double, C.c_int, C.POINTER(C.c_longlong), _dp]
+    a, b = _vec(qa), _vec(qb)
+    out = (C.c_longlong * 5)()
+    res = np.zeros(5)
+    rc = _opc.oracle_op_count(int(what), int(r), _ptr(a), _ptr(b), float(phia), float(phib),
+                              float(gamma), int(surf), out, _ptr(res))
+    assert rc == 0, what
+    return dict(zip(OP_CLASSES, [int(x) for x in out])), res
+
+
+def flops(counts) -> int:
+    """Flops of an op_count result: every class counts one."""
+    return sum(counts.values())
 
 
 def _ptr(a):

@@ -62,6 +62,9 @@
 #define TERM_FACE 2
 #define TERM_SRC 4
 
+/* the scalar of the pointwise physics in esdg_pointwise.h: plain FP64 here */
+typedef double real;
+
 typedef struct {
     int N, Nq, Np;
     int K[3];
@@ -405,26 +408,7 @@ void oracle_tables(void *mp, double *xi, double *w, double *D, double *S)
 /* ------------------------------------------------------------------------ */
 /* Pointwise physics                                                         */
 /* ------------------------------------------------------------------------ */
-
-/* Pressure from the conservative state, with E containing rho*phi:
- * P = (gamma-1) (E - |U|^2/(2 rho) - rho phi)   (Sec. 2). */
-static double pressure(const double q[5], double phi, double gamma)
-{
-    double ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
-    return (gamma - 1.0) * (q[4] - ke - q[0] * phi);
-}
-
-/* Logarithmic mean {{a}}_log = [[a]] / [[ln a]] (Sec. 4.1), with the
- * near-equal branch by the Taylor series of 2 atanh(f)/f in u = f^2,
- * f = (b-a)/(b+a). */
-double oracle_logmean(double a, double b)
-{
-    double f = (b - a) / (b + a);
-    double u = f * f;
-    if (u < 1e-4)
-        return (a + b) / (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0))));
-    return (b - a) / (log(b) - log(a));
-}
+#include "esdg_pointwise.h"
 
 /* Physical Euler flux in direction r (conservative form of Eq:euler). */
 void oracle_euler_flux(int r, const double q[5], double phi, double gamma, double f[5])
@@ -436,132 +420,6 @@ void oracle_euler_flux(int r, const double q[5], double phi, double gamma, doubl
     f[4] = (q[4] + p) * ur;
 }
 
-/* Two-point volume flux F_r(a, b) for own node a and partner b.
- * Mass and momentum follow the paper's momentum flux
- *   f^m_c = f^rho {{u_c}} + delta_cr (p* + rho_hat [[phi]] / 2),
- *   rho_hat = {{b}} {{rho}}_log / b_a,  b = rho / (2 p)   (Sec. 4.1)
- * with f^rho = {{rho}}_log {{u_r}} and p* = {{p}}; the energy flux is the
- * Ranocha-type form plus {{phi}} f^rho (E contains rho*phi).  The result is
- * not symmetric in (a, b) because of the gravity term. */
-void oracle_two_point_flux(int r, const double qa[5], const double qb[5], double phia,
-                           double phib, double gamma, double F[5])
-{
-    double ra = qa[0], rb = qb[0];
-    double ua[3], ub[3];
-    for (int c = 0; c < 3; ++c) {
-        ua[c] = qa[1 + c] / ra;
-        ub[c] = qb[1 + c] / rb;
-    }
-    double pa = pressure(qa, phia, gamma), pb = pressure(qb, phib, gamma);
-    double rho_ln = oracle_logmean(ra, rb);
-    double z_ln = oracle_logmean(ra / pa, rb / pb); /* {{rho/p}}_log */
-    double ba = ra / (2.0 * pa), bb = rb / (2.0 * pb);
-    double frho = rho_ln * 0.5 * (ua[r] + ub[r]);
-    double rho_hat = 0.5 * (ba + bb) * rho_ln / ba;
-    double grav_term = 0.5 * rho_hat * (phib - phia);
-    double pmean = 0.5 * (pa + pb);
-    F[0] = frho;
-    for (int c = 0; c < 3; ++c)
-        F[1 + c] = frho * 0.5 * (ua[c] + ub[c]) + (c == r ? pmean + grav_term : 0.0);
-    double uaub = ua[0] * ub[0] + ua[1] * ub[1] + ua[2] * ub[2];
-    F[4] = frho * (1.0 / ((gamma - 1.0) * z_ln) + 0.5 * uaub + 0.5 * (phia + phib)) +
-           0.5 * (pa * ub[r] + pb * ua[r]);
-}
-
-/* Entropy-stable matrix dissipation D for a face normal along axis r (the
- * Roe-type dissipation the paper adds to the entropy-conservative face flux,
- * Sec. 3; the formula is cited there, not printed, and is read here as the
- * standard construction).  With the averaged state
- *   rho_hat = {{rho}}_log,  u_hat = {{u}},  p_hat = {{rho}} / (2 {{b}}),
- *   |u|^2_bar = 2 |u_hat|^2 - {{|u|^2}},
- *   h_hat = gamma / (2 (gamma - 1) {{b}}_log) + |u|^2_bar / 2,
- *   a_hat = sqrt(gamma p_hat / rho_hat),
- * R holds the right eigenvectors of the normal flux Jacobian (acoustic,
- * entropy, two shear, acoustic), |lambda| the moduli of their eigenvalues
- * u_n -+ a, u_n, u_n, u_n, and t the diagonal scaling for which
- * R diag(t) R^T = dq/dv at equal states:
- *   D = R diag(|lambda| t) R^T [[v]],   [[v]] = v(q+) - v(q-).
- * D is symmetric positive semi-definite in [[v]], so it only removes
- * entropy, and it does not depend on the sign of the normal.  Both sides of
- * a face share phi and E contains rho*phi: D is formed for the state without
- * the potential energy, (rho, m, E - rho phi), whose entropy variables lack
- * the 2 b phi term, and the energy component then gains phi times the mass
- * component (that map is linear with unit diagonal, so this is the same
- * operator written for the total energy).
- * Pins: the small-jump limit |A| [[q]], entropy stability, antisymmetry and
- * an exactly kept stationary contact (which fixes the log-mean in h_hat).
- * The averages chosen for p_hat, |u|^2_bar and a_hat enter only at second
- * order in the jump: beyond that they are a reading, parity unpinned. */
-static void matrix_dissipation(int r, const double qm[5], const double qp[5], double phi,
-                               double gamma, double D[5])
-{
-    double gm1 = gamma - 1.0;
-    double rm = qm[0], rp = qp[0], um[3], up[3];
-    for (int c = 0; c < 3; ++c) {
-        um[c] = qm[1 + c] / rm;
-        up[c] = qp[1 + c] / rp;
-    }
-    double pm = pressure(qm, phi, gamma), pp = pressure(qp, phi, gamma);
-    double bm = rm / (2.0 * pm), bp = rp / (2.0 * pp);
-    double uum = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
-    double uup = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
-
-    /* averaged state */
-    double rho_hat = oracle_logmean(rm, rp);
-    double b_ln = oracle_logmean(bm, bp);
-    double uh[3];
-    for (int c = 0; c < 3; ++c) uh[c] = 0.5 * (um[c] + up[c]);
-    double p_hat = 0.5 * (rm + rp) / (2.0 * 0.5 * (bm + bp));
-    double u2bar = 2.0 * (uh[0] * uh[0] + uh[1] * uh[1] + uh[2] * uh[2]) - 0.5 * (uum + uup);
-    double h_hat = gamma / (2.0 * gm1 * b_ln) + 0.5 * u2bar;
-    double a_hat = sqrt(gamma * p_hat / rho_hat);
-
-    /* jump of the entropy variables without the potential energy,
-     * v = ((gamma - s)/(gamma - 1) - b |u|^2, 2 b u, -2 b), s = ln p - gamma ln rho;
-     * a jump of logarithms is taken as the logarithm of the ratio */
-    double ds = log(pp / pm) - gamma * log(rp / rm);
-    double dv[5];
-    dv[0] = -ds / gm1 - (bp * uup - bm * uum);
-    for (int c = 0; c < 3; ++c) dv[1 + c] = 2.0 * (bp * up[c] - bm * um[c]);
-    dv[4] = -2.0 * (bp - bm);
-
-    /* eigenvectors (columns), normal e_r, tangents the other two axes */
-    int t1 = (r + 1) % 3, t2 = (r + 2) % 3;
-    double un = uh[r];
-    double Rm[5][5];
-    memset(Rm, 0, sizeof(Rm));
-    Rm[0][0] = 1.0;
-    Rm[0][1] = 1.0;
-    Rm[0][4] = 1.0;
-    for (int c = 0; c < 3; ++c) {
-        Rm[1 + c][0] = uh[c] - (c == r ? a_hat : 0.0);
-        Rm[1 + c][1] = uh[c];
-        Rm[1 + c][4] = uh[c] + (c == r ? a_hat : 0.0);
-    }
-    Rm[1 + t1][2] = 1.0;
-    Rm[1 + t2][3] = 1.0;
-    Rm[4][0] = h_hat - a_hat * un;
-    Rm[4][1] = 0.5 * u2bar;
-    Rm[4][2] = uh[t1];
-    Rm[4][3] = uh[t2];
-    Rm[4][4] = h_hat + a_hat * un;
-    double lam[5] = {fabs(un - a_hat), fabs(un), fabs(un), fabs(un), fabs(un + a_hat)};
-    double tsc[5] = {rho_hat / (2.0 * gamma), rho_hat * gm1 / gamma, p_hat, p_hat,
-                     rho_hat / (2.0 * gamma)};
-
-    double w[5];
-    for (int k = 0; k < 5; ++k) {
-        double acc = 0.0;
-        for (int v = 0; v < 5; ++v) acc += Rm[v][k] * dv[v];
-        w[k] = lam[k] * tsc[k] * acc;
-    }
-    for (int v = 0; v < 5; ++v) {
-        double acc = 0.0;
-        for (int k = 0; k < 5; ++k) acc += Rm[v][k] * w[k];
-        D[v] = acc;
-    }
-    D[4] += phi * D[0];
-}
 
 /* The matrix dissipation above for a general unit normal n (curved faces).
  * The acoustic and entropy eigenvectors keep their form with n in place of
@@ -633,32 +491,6 @@ static void matrix_dissipation_vec(const double nv[3], const double qm[5], const
     D[4] += phi * D[0];
 }
 
-/* Normal face flux F* . n for the face with outward normal n = s e_r (s = +-1):
- * s f_r(q-, q+) - lambda/2 (q+ - q-) with lambda = max(|u.n| + c) (Rusanov),
- * s f_r(q-, q+) - D/2 with the matrix dissipation above, or without
- * dissipation for the entropy-conservative face flux.  Faces have
- * phi+ = phi-. */
-void oracle_surface_flux(int r, int s, const double qm[5], const double qp[5], double phim,
-                         double phip, double gamma, int surf, double Fn[5])
-{
-    double F[5];
-    oracle_two_point_flux(r, qm, qp, phim, phip, gamma, F);
-    if (surf == SURF_MATRIX) {
-        double D[5];
-        matrix_dissipation(r, qm, qp, phim, gamma, D);
-        for (int v = 0; v < 5; ++v) Fn[v] = s * F[v] - 0.5 * D[v];
-        return;
-    }
-    double lam = 0.0;
-    if (surf == SURF_RUSANOV) {
-        double pm = pressure(qm, phim, gamma), pp = pressure(qp, phip, gamma);
-        double cm = sqrt(gamma * pm / qm[0]), cp = sqrt(gamma * pp / qp[0]);
-        double lm = fabs(qm[1 + r] / qm[0]) + cm;
-        double lp = fabs(qp[1 + r] / qp[0]) + cp;
-        lam = lm > lp ? lm : lp;
-    }
-    for (int v = 0; v < 5; ++v) Fn[v] = s * F[v] - 0.5 * lam * (qp[v] - qm[v]);
-}
 
 /* Face flux along a general (unnormalised) normal Nv = s J a^r of a curved
  * element: sum_d Nv_d f_d(q-, q+) minus the Rusanov dissipation
@@ -830,8 +662,7 @@ static void rhs_element_curved(const omesh *m, const double *q, double *R, doubl
             }
         }
         if (mask & TERM_SRC) {
-            acc[1] += m->cor_f * qa[2];
-            acc[2] -= m->cor_f * qa[1];
+            coriolis_source(m->cor_f, qa, acc);
             gacc[1] += fabs(m->cor_f * qa[2]);
             gacc[2] += fabs(m->cor_f * qa[1]);
         }
@@ -908,9 +739,7 @@ static void rhs_element(const omesh *m, const double *q, double *R, double *gros
                     }
                 }
                 if (mask & TERM_SRC) {
-                    /* -Omega x U with Omega = f z_hat */
-                    acc[1] += m->cor_f * qa[2];
-                    acc[2] -= m->cor_f * qa[1];
+                    coriolis_source(m->cor_f, qa, acc);
                     gacc[1] += fabs(m->cor_f * qa[2]);
                     gacc[2] += fabs(m->cor_f * qa[1]);
                 }
@@ -1039,10 +868,7 @@ static void lsrk_advance(int64_t n, double *q, double *dq, double *R, double t, 
 {
     for (int s = 0; s < 5; ++s) {
         f(ctx, q, R, t + LSRK_C[s] * dt);
-        for (int64_t i = 0; i < n; ++i) {
-            dq[i] = LSRK_A[s] * dq[i] + dt * R[i];
-            q[i] = q[i] + LSRK_B[s] * dq[i];
-        }
+        for (int64_t i = 0; i < n; ++i) lsrk_update(LSRK_A[s], LSRK_B[s], dt, R[i], &dq[i], &q[i]);
     }
 }
 

@@ -1,18 +1,33 @@
 """Algorithmic work and traffic of the fused ES-DGSEM stage, and the MI355X
 roofline it is measured against.
 
-Algorithmic counts come from the formulas the kernels evaluate (each +, -,
-*, /, sqrt and log counts one flop, an FMA two), not from executed
-instructions:
+Algorithmic flops are the operation counts of the oracle's own pointwise
+physics (each +, -, *, /, sqrt and log one flop; the oracle has no FMA),
+mapped onto the work a node, a node pair and a face node need once:
 
-  pair (x or y line, series branch of both log-means)   73 flops
-      two log-means 11 + 11, f^rho 3, momentum 12, u_a.u_b 5,
-      energy 11, accumulation into both nodes 20
-  pair on a z line (adds the gravity term and its partner scaling) 87
-  per-node precompute (primitives, rho/p, two logs, 1/z)            19
-  face node (both states' primitives, log-means, flux, Rusanov
-      dissipation, lift)                                             126
-  per-node finish (phase sums, Coriolis, LSRK update)                 55
+  PRECOMP    = C_node                                   per node: u, p, rho/p, b
+  PAIR_XY    = C_flux - 2 C_node - C_grav + SCATTER     unordered pair, x or y line
+  PAIR_Z     = C_flux - 2 C_node + C_grav + SCATTER     unordered pair, z line
+  FACE_NODE  = C_face - C_node - C_grav + LIFT          face node, Rusanov
+  FINISH     = 5 C_update + C_source + PHASE            per node, stage
+  FINISH_RHS = C_source + PHASE                         per node, RHS only
+
+with C_node the per-node quantities of the two-point flux, C_flux one
+two-point flux evaluation (series branch of both log-means), C_grav its
+gravity term with the addition into the normal momentum, C_face one face
+flux with Rusanov dissipation, C_update one value of the LSRK stage update
+and C_source the Coriolis source of one node.  The flux evaluates both
+nodes' quantities, which a node needs only once (the precompute); a pair of
+an x or y line has no gravity term (phi is constant along it), and on a z
+line the partner's flux differs from the own node's only in its gravity
+term; at a face the own node's quantities come from the precompute and the
+geopotential is continuous.  The kernel-structure terms are
+  SCATTER = 20  a pair's flux into both nodes' sums: 2 x 5 x (mul + add)
+  LIFT    = 10  a face flux into its node's sum: 5 x (mul + add)
+  PHASE   = 25  per node the three directions' sums, each scaled by 2/h_r
+                and added: 5 x (3 mul + 2 add).
+tests/test_perfmodel_counts.py recomputes every constant from the oracle's
+operation counter (oracle_op_count) through this mapping.
 
 Pairs per node: 3N/2 (Nq(Nq-1)/2 pairs per line, Nq^2 lines per direction,
 three directions, Nq^3 nodes).  Face nodes per node: 6/Nq.
@@ -34,7 +49,15 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
 FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 
-PAIR_XY, PAIR_Z, PRECOMP, FACE_NODE, FINISH_STAGE, FINISH_RHS = 73, 87, 19, 126, 55, 20
+# oracle operation counts (series branch of both log-means) and the mapping above
+C_NODE, C_FLUX, C_GRAV, C_FACE, C_UPDATE, C_SOURCE = 18, 104, 8, 163, 5, 4
+SCATTER, LIFT, PHASE = 20, 10, 25
+PRECOMP = C_NODE
+PAIR_XY = C_FLUX - 2 * C_NODE - C_GRAV + SCATTER
+PAIR_Z = C_FLUX - 2 * C_NODE + C_GRAV + SCATTER
+FACE_NODE = C_FACE - C_NODE - C_GRAV + LIFT
+FINISH_STAGE = 5 * C_UPDATE + C_SOURCE + PHASE
+FINISH_RHS = C_SOURCE + PHASE
 
 
 def pairs_per_node(N: int) -> float:
