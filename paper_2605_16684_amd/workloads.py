@@ -173,11 +173,12 @@ def state_iso_rest(xyz, spec: MeshSpec, T=300.0):
 
 
 def state_bubble(xyz, spec: MeshSpec, seed: Optional[int] = None, theta0=300.0, amp=0.5,
-                 rc=250.0, centre=(500.0, 500.0, 350.0)):
-    """Neutral atmosphere with the smooth cosine bubble
-    dtheta = amp (1 + cos(pi r/rc))/2 for r <= rc (Sec. 5.1); p is the
-    background hydrostatic pressure, u = 0.  A seed jitters the centre
-    (+-50 m) and the amplitude (x [0.8, 1.2])."""
+                 rc=250.0, centre=(500.0, 500.0, 350.0), shape="smooth"):
+    """Neutral atmosphere with a warm bubble (Sec. 5.1): the smooth cosine
+    bubble dtheta = amp (1 + cos(pi r/rc))/2 for r <= rc, or with
+    shape="sharp" the discontinuous one, dtheta = amp for r <= rc, 0 outside;
+    p is the background hydrostatic pressure, u = 0.  A seed jitters the
+    centre (+-50 m) and the amplitude (x [0.8, 1.2])."""
     if seed is not None:
         rng = np.random.default_rng(seed)
         centre = tuple(c + float(rng.uniform(-50.0, 50.0)) for c in centre)
@@ -186,9 +187,14 @@ def state_bubble(xyz, spec: MeshSpec, seed: Optional[int] = None, theta0=300.0, 
     x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
     pi, p = neutral(z, theta0, gas_R=spec.gas_R, grav=spec.grav, gamma=spec.gamma)
     r = xp.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2)
-    rcl = xp.clip(r, None, rc) if xp is np else r.clamp(max=rc)
-    dth = amp * 0.5 * (1.0 + xp.cos(math.pi * rcl / rc))
-    dth = dth * (r <= rc)
+    if shape == "sharp":
+        dth = amp * (r <= rc)
+    elif shape == "smooth":
+        rcl = xp.clip(r, None, rc) if xp is np else r.clamp(max=rc)
+        dth = amp * 0.5 * (1.0 + xp.cos(math.pi * rcl / rc))
+        dth = dth * (r <= rc)
+    else:
+        raise ValueError(shape)
     rho = p / (spec.gas_R * (theta0 + dth) * pi)
     zero = xp.zeros_like(z)
     return _pack(rho, zero, zero, zero, p, z, spec.gamma, spec.grav)
@@ -228,7 +234,7 @@ def reference_state(xyz, spec: MeshSpec, kind: str):
     """Hydrostatic reference (rho_r, p_r) per node for the mixed-precision
     path: [e][n] arrays."""
     z = xyz[:, 2]
-    if kind == "bubble":
+    if kind in ("bubble", "bubble_sharp"):
         pi, p = neutral(z, gas_R=spec.gas_R, grav=spec.grav, gamma=spec.gamma)
         return p / (spec.gas_R * 300.0 * pi), p
     if kind == "channel":
@@ -243,6 +249,8 @@ def make_state(kind: str, xyz, spec: MeshSpec, seed=0):
         return state_iso_pert(xyz, spec, seed)
     if kind == "bubble":
         return state_bubble(xyz, spec, None if seed == 0 else seed)
+    if kind == "bubble_sharp":
+        return state_bubble(xyz, spec, None if seed == 0 else seed, shape="sharp")
     if kind == "channel":
         return state_channel(xyz, spec, seed)
     if kind == "iso_rest":
