@@ -148,9 +148,7 @@ def precision_block(esdg, W, torch, steps=100, workload="c3"):
     s64, q64, a0, a1 = run(m64, dt, steps)
     s32, q32, b0, b1 = run(m32, dt, steps)
     dq = q32 - q64
-    state = [float(torch.linalg.norm(dq[:, 0]) / torch.linalg.norm(q64[:, 0])),
-             float(torch.linalg.norm(dq[:, 1:4]) / torch.linalg.norm(q64[:, 1:4])),
-             float(torch.linalg.norm(dq[:, 4]) / torch.linalg.norm(q64[:, 4]))]
+    state = [float(torch.linalg.norm(dq[:, v]) / torch.linalg.norm(q64[:, v])) for v in range(5)]
     out.update({
         "fp64": {"rhs_ms": t64 * 1e3, "rhs_dof_per_s": nn / t64, "step_ms": s64 * 1e3,
                  "dof_rhs_per_s": nn * 5 / s64,
@@ -163,13 +161,60 @@ def precision_block(esdg, W, torch, steps=100, workload="c3"):
                        "energy_drift": abs(b1[2] - b0[2]) / abs(b0[2]),
                        "entropy_change": (b1[0] - b0[0]) / abs(b0[0])},
         "rhs_speedup": t64 / t32, "step_speedup": s64 / s32,
+        # plain relative L2 per conserved variable (rho, rho u, rho v, rho w, rho E);
+        # the tests also bound the error against the gross term scale
         "rhs_rel_l2_vs_fp64_per_var": net,
         "steps": steps, "dt": dt,
-        "state_rel_l2_vs_fp64_after_steps": {"rho": state[0], "momentum": state[1],
-                                             "energy": state[2]},
+        "state_rel_l2_vs_fp64_after_steps_per_var": state,
     })
     m64.close()
     m32.close()
+    return out
+
+
+def symmetry_block(esdg, W, torch, steps=1000):
+    """The rising bubble (32^3 elements, N = 4, walls) with the sharp and the
+    smooth potential-temperature bubble, `steps` LSRK(5,4) steps in FP64 and
+    in FP32-mixed: the mirror-symmetry defect about the vertical mid-planes
+    x = 500 m and y = 500 m per conserved variable, measured against the
+    deviation from the hydrostatic background (the exact solution keeps the
+    symmetry, rounding does not), and the drift of mass, energy and entropy."""
+    from paper_2605_16684_amd import symmetry as S
+    wl = W.rising_bubble()
+    spec = wl.mesh
+    probe = esdg.Mesh(spec)
+    xyz = probe.coords()
+    probe.close()
+    qref = W.state_bubble(xyz, spec, amp=0.0).contiguous()
+    out = {"workload": wl.name, "steps": steps}
+    for shape, kind in (("sharp", "bubble_sharp"), ("smooth", "bubble")):
+        q0 = W.make_state(kind, xyz, spec).contiguous()
+        rr, pr = W.reference_state(xyz, spec, kind)
+        res = {}
+        for prec in ("fp64", "fp32_mixed"):
+            if prec == "fp64":
+                m = esdg.Mesh(spec)
+            else:
+                m = esdg.Mesh(spec, precision=esdg.FP32_MIXED, ref_rho=rr.contiguous(),
+                              ref_p=pr.contiguous())
+            q = q0.clone()
+            dq = torch.zeros_like(q)
+            dt = m.cfl_dt(q, wl.cfl)
+            e0 = m.entropy(q)
+            m.lsrk_run(q, dq, dt, steps)
+            e1 = m.entropy(q)
+            m.check()
+            dx = S.defect(q, spec.K, spec.N, 0, qref)
+            dy = S.defect(q, spec.K, spec.N, 1, qref)
+            res[prec] = {"dt": dt, "defect_x_per_var": dx, "defect_y_per_var": dy,
+                         "defect_max": max(max(dx), max(dy)),
+                         "mass_rel_drift": (e1[1] - e0[1]) / abs(e0[1]),
+                         "energy_rel_drift": (e1[2] - e0[2]) / abs(e0[2]),
+                         "entropy_rel_change": (e1[0] - e0[0]) / abs(e0[0])}
+            m.close()
+            del q, dq
+        out[shape] = res
+        del q0, rr, pr
     return out
 
 
@@ -373,6 +418,9 @@ def main():
     ap.add_argument("--precision-workload", default="c3")
     ap.add_argument("--precision-steps", type=int, default=100,
                     help="LSRK steps of each precision in the FP64 vs FP32-mixed run")
+    ap.add_argument("--no-symmetry", action="store_true",
+                    help="skip the long sharp/smooth bubble runs with the symmetry defect")
+    ap.add_argument("--symmetry-steps", type=int, default=1000)
     ap.add_argument("--no-serving", action="store_true", help="skip the ensemble serving run")
     ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--surface", default="rusanov", choices=("rusanov", "matrix", "ec"),
@@ -553,6 +601,10 @@ def main():
         log("[bench] FP64 vs FP32-mixed ...")
         out["precision"] = precision_block(esdg, W, torch, steps=args.precision_steps,
                                            workload=args.precision_workload)
+        torch.cuda.empty_cache()
+    if not args.no_symmetry:
+        log("[bench] sharp and smooth bubbles, symmetry defect ...")
+        out["bubble_symmetry"] = symmetry_block(esdg, W, torch, steps=args.symmetry_steps)
         torch.cuda.empty_cache()
     if args.sweep:
         log("[bench] size sweep ...")
