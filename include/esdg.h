@@ -152,6 +152,21 @@ int esdg_rhs_terms(esdg_mesh_t mesh, const double *q_dev, double *r_dev, int32_t
  * second state buffer holds the ping-pong copy. */
 int esdg_lsrk_step(esdg_mesh_t mesh, double *q_dev, double *dq_dev, double t, double dt);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step
+ * of esdg_lsrk_step, same kernels and the same bits, with its ping-pong
+ * state in a library-owned device array of 8,388,608 doubles (64 MiB) per
+ * device instead of the mesh's lazily allocated buffer.  It calls no
+ * hipMalloc/hipFree.  The array is set up once per device when the first
+ * mesh is created there and is held until the process ends.  Meshes whose
+ * state_len exceeds 8,388,608 doubles are rejected (ESDG_EINVAL) before
+ * any work is enqueued.  Every call on a device shares that device's
+ * array: calls that overlap on one device (several host threads, or meshes
+ * on different streams whose steps can run concurrently) race and must be
+ * serialised by the caller.  The array's contents between calls are
+ * meaningless (each step writes it before reading it). */
+int esdg_lsrk_step_noalloc(esdg_mesh_t mesh, double *q_dev, double *dq_dev, double t, double dt);
+
 /* nsteps LSRK(5,4) steps in place, replayed from a captured HIP graph of
  * two steps (re-captured when q, dq or dt change). */
 int esdg_lsrk_run(esdg_mesh_t mesh, double *q_dev, double *dq_dev, double t0, double dt,

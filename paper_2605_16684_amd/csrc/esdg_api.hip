@@ -148,6 +148,17 @@ OrderTables make_order_tables(int N)
 
 std::mutex g_init_mu;
 bool g_dev_init[64];
+double *g_scratch[64];  // device address of `scratch` on each device (set at init)
+
+}  // namespace
+
+// Device memory of the allocation-free step (esdg_lsrk_step_noalloc): the
+// ping-pong state of its five stages.  One array per device, held until the
+// process ends; host code reaches it only through g_scratch[device].
+constexpr int64_t kNoallocMaxDoubles = (int64_t)1 << 23;  // 64 MiB
+static __device__ __align__(256) double scratch[kNoallocMaxDoubles];
+
+namespace {
 
 int ensure_tables(int dev)
 {
@@ -158,6 +169,9 @@ int ensure_tables(int dev)
     for (int N = 1; N <= NQ_MAX - 1; ++N) tabs[N - 1] = make_order_tables(N);
     std::memset(&tabs[NQ_MAX - 1], 0, sizeof(OrderTables));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_tab), tabs, sizeof tabs, 0, hipMemcpyHostToDevice));
+    void *sp = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+    g_scratch[dev] = (double *)sp;
     g_dev_init[dev] = true;
     return ESDG_OK;
 }
@@ -906,6 +920,27 @@ int esdg_lsrk_step(esdg_mesh_t m, double *q, double *dq, double t, double dt)
     // five stages end in the mesh's second buffer
     HIP_TRY(hipMemcpyAsync(q, m->d_q2, sizeof(double) * (size_t)m->state_len,
                            hipMemcpyDeviceToDevice, m->stream));
+    return ESDG_OK;
+}
+
+int esdg_lsrk_step_noalloc(esdg_mesh_t m, double *q, double *dq, double t, double dt)
+{
+    (void)t;
+    int rc = check_mesh(m);
+    if (rc || (rc = check_ptr(q, "q")) || (rc = check_ptr(dq, "dq"))) return rc;
+    if (overlaps(q, dq, m->state_len)) return fail(ESDG_EINVAL, "q and dq must not overlap");
+    if (m->state_len > kNoallocMaxDoubles)
+        return fail(ESDG_EINVAL,
+                    "state of %lld doubles exceeds the %lld-double device scratch of "
+                    "esdg_lsrk_step_noalloc",
+                    (long long)m->state_len, (long long)kNoallocMaxDoubles);
+    if ((rc = set_device(m))) return rc;
+    double *s = g_scratch[m->device];
+    if (!s) return fail(ESDG_EINVAL, "device scratch of device %d is not set up", m->device);
+    rc = enqueue_step(m, q, s, dq, dt, true);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(q, s, sizeof(double) * (size_t)m->state_len, hipMemcpyDeviceToDevice,
+                           m->stream));
     return ESDG_OK;
 }
 

@@ -68,6 +68,8 @@ SIGNATURES = {
     "esdg_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
     "esdg_rhs_terms": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "esdg_lsrk_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double]),
+    "esdg_lsrk_step_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                         C.c_double]),
     "esdg_lsrk_run": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                 C.c_int32]),
     "esdg_entropy": (C.c_int, [C.c_void_p, C.c_void_p, _dp]),
@@ -253,6 +255,13 @@ class Mesh:
     def lsrk_step(self, q, dq, dt: float, t: float = 0.0):
         self._bind()
         _check(lib.esdg_lsrk_step(self._h, self._state(q, "q"), self._state(dq, "dq"), t, dt))
+
+    def lsrk_step_noalloc(self, q, dq, dt: float, t: float = 0.0):
+        """lsrk_step with the library's per-device scratch array in place of
+        the mesh's ping-pong buffer (no device allocation)."""
+        self._bind()
+        _check(lib.esdg_lsrk_step_noalloc(self._h, self._state(q, "q"), self._state(dq, "dq"),
+                                          t, dt))
 
     def lsrk_run(self, q, dq, dt: float, nsteps: int, t0: float = 0.0):
         self._bind()
