@@ -15,8 +15,9 @@
 // The geopotential varies along every line of a curved element, so the
 // gravity term appears in all three directions.  The line-per-lane layout,
 // the LDS accumulator of the affine kernel and the face handling are kept;
-// the metric terms, 1/J and phi are read per node from HBM (88 B per node
-// per stage beyond the state).
+// the metric terms and 1/J are read per node from HBM, and phi once per
+// element by the x phase, which leaves it in LDS for the other phases and
+// the finish (88 B per node per stage beyond the state).
 #pragma once
 
 #include "esdg_device.hpp"
@@ -229,7 +230,7 @@ __device__ __forceinline__ void face_flux_vec(const Node &a, const Cons &qm, con
 template <int NQ, int R, bool KEEP = false>
 __device__ __forceinline__ void line_terms_curved(const CurvedParams &C, const OrderTables &tb,
                                                   int m, int64_t e, const int ec[3],
-                                                  double acc[NQ][5],
+                                                  double *sphi, double acc[NQ][5],
                                                   double (*qkeep)[5] = nullptr)
 {
     constexpr int NQ3 = NQ * NQ * NQ;
@@ -246,7 +247,14 @@ __device__ __forceinline__ void line_terms_curved(const CurvedParams &C, const O
     for (int t = 0; t < NQ; ++t) {
         const int n = line_node<NQ, R>(m, t);
         load_cons(P.q_in, e, NQ3, n, qc[t]);
-        ph[t] = C.phi[e * NQ3 + n];
+        if (R == 0) {
+            // the x lines cover the element: its geopotential goes to LDS
+            // for the other phases and the finish
+            ph[t] = C.phi[e * NQ3 + n];
+            sphi[n] = ph[t];
+        } else {
+            ph[t] = sphi[n];
+        }
 #pragma unroll
         for (int d = 0; d < 3; ++d) jr[t][d] = 0.5 * C.Ja[((e * 3 + R) * 3 + d) * NQ3 + n];
     }
@@ -338,6 +346,7 @@ __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
 {
     constexpr int NQ2 = NQ * NQ, NQ3 = NQ2 * NQ;
     __shared__ double sacc[5][EPW][NQ3];
+    __shared__ double sphi[EPW][NQ3];
     const StageParams &P = C.s;
     const OrderTables &tb = c_tab[NQ - 2];
     const int tid = threadIdx.x;
@@ -355,12 +364,15 @@ __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
     // x phase
     if (act) {
         if (vol_or_face) {
-            line_terms_curved<NQ, 0>(C, tb, m, e, ec, acc);
+            line_terms_curved<NQ, 0>(C, tb, m, e, ec, sphi[el], acc);
         } else {
 #pragma unroll
-            for (int t = 0; t < NQ; ++t)
+            for (int t = 0; t < NQ; ++t) {
+                const int n = line_node<NQ, 0>(m, t);
+                sphi[el][n] = C.phi[e * NQ3 + n];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) acc[t][v] = 0.0;
+            }
         }
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
@@ -372,7 +384,7 @@ __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
     __syncthreads();
     // y phase
     if (act && vol_or_face) {
-        line_terms_curved<NQ, 1>(C, tb, m, e, ec, acc);
+        line_terms_curved<NQ, 1>(C, tb, m, e, ec, sphi[el], acc);
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             const int n = line_node<NQ, 1>(m, t);
@@ -387,7 +399,7 @@ __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
     constexpr bool HOLD = curved_holds_states<NQ>();
     double qv[HOLD ? NQ : 1][5];
     if (vol_or_face) {
-        line_terms_curved<NQ, 2, HOLD>(C, tb, m, e, ec, acc, qv);
+        line_terms_curved<NQ, 2, HOLD>(C, tb, m, e, ec, sphi[el], acc, qv);
     } else {
 #pragma unroll
         for (int t = 0; t < NQ; ++t)
@@ -439,7 +451,7 @@ __device__ __forceinline__ void stage_curved_body(const CurvedParams &C, int lb)
         if (P.flag) {
             const double r = qn[0];
             const double kin = qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3];
-            const double eint = qn[4] - 0.5 * kin / r - r * C.phi[e * NQ3 + n];
+            const double eint = qn[4] - 0.5 * kin / r - r * sphi[el][n];
             bad |= !(r > 0.0) || !(eint > 0.0);
         }
     }

@@ -633,14 +633,15 @@ constexpr int block_threads()
 }
 
 // Whether the z phase holds its line's states in registers for the finish.
-// At N=5 holding them costs half the occupancy (256 VGPRs plus 18 AGPRs
-// against 226 when the finish reads them again: 2.5-16% faster steps); at
-// N=6-8 reading them again does not reach two waves and was slower, and up
+// At N=5 and N=6 reading them again in the finish fits two waves per SIMD
+// without spills, where holding them costs half the occupancy (2.5-16% and
+// 11% faster steps); at N=7 and N=8 reading them again does not reach two
+// waves (forcing two waves spills 260 B per lane at N=7) and was slower; up
 // to N=4 the kernel fits two waves either way.
 template <int NQ>
 constexpr bool stage_holds_states()
 {
-    return NQ != 6;
+    return NQ != 6 && NQ != 7;
 }
 
 // One workgroup handles EPW elements (logical block lb of the mesh); lane

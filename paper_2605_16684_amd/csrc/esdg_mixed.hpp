@@ -32,15 +32,16 @@ struct MixedParams {
     const float *rr_mom;    // [e][3][n] R(q_r) momentum components
 };
 
-// Per-node quantities of one line (FP32), plus the perturbation data.
+// Per-node quantities of one line (FP32), plus the perturbation data.  The
+// per-node logarithms of the log-mean branch live in arrays of their own,
+// filled only where the general pair loop runs.
 struct NodeF {
     float r, h0, h1, h2, hp, z, zi;  // full-variable primitives (halved u, p)
-    float lr, lz;                    // ln rho, ln(z * scale)
     float hpp;                       // p'/2
     float rp;                        // rho' = rho - rho_r
     float rr;                        // rho_r
-    float zr, izr;                   // z_r = rho_r / p_r and its reciprocal
-    float beta, ib1;                 // b/b_r - 1 and 1/(1 + beta)
+    float zr;                        // z_r = rho_r / p_r
+    float beta;                      // b/b_r - 1
 };
 
 template <int R>
@@ -86,68 +87,111 @@ __device__ __forceinline__ float inv_log_mean_f(float a, float b, float la, floa
     return ser ? 2.0f * r * (1.0f + u * (IF1 + u * (IF2 + u * (IF3 + u * IF4)))) : (lb - la) * r;
 }
 
-// {{rho}}_log - {{rho_r}}_log from the perturbations rho', in one of three
-// forms, none of which subtracts two nearly equal FP32 numbers:
-//  - both pairs in the series branch:  L = s g(u)/2,
+// A line whose extreme pair satisfies |b-a| < 0.09999 (b+a) has every pair in
+// the series range of the FP32 rule (slightly tighter, so that no pair of a
+// line declared series-only would select the log branch by itself).
+constexpr float LMF_SQRT_LINE = 0.09999f;
+
+template <int NQ>
+__device__ __forceinline__ bool line_spread_f(const float x[NQ])
+{
+    float mn = x[0], mx = x[0];
+#pragma unroll
+    for (int t = 1; t < NQ; ++t) {
+        mn = fminf(mn, x[t]);
+        mx = fmaxf(mx, x[t]);
+    }
+    return !(mx - mn < LMF_SQRT_LINE * (mx + mn));
+}
+
+// Series forms with the 1/2 of the mean folded into the coefficients.
+constexpr float GH0 = 0.5f, GH1 = 0.5f * GF1, GH2 = 0.5f * GF2, GH3 = 0.5f * GF3,
+                GH4 = 0.5f * GF4;
+
+__device__ __forceinline__ float log_mean_series_f(float a, float b)
+{
+    const float d = b - a, s = a + b;
+    const float x = d * rcpf(s);
+    const float u = x * x;
+    return s * (GH0 - u * (GH1 + u * (GH2 + u * (GH3 + u * GH4))));
+}
+
+__device__ __forceinline__ float inv_log_mean_series_f(float a, float b)
+{
+    const float d = b - a, s = a + b;
+    const float r = rcpf(s);
+    const float f = d * r;
+    const float u = f * f;
+    return (r + r) * (1.0f + u * (IF1 + u * (IF2 + u * (IF3 + u * IF4))));
+}
+
+// {{rho}}_log - {{rho_r}}_log from the perturbations rho' (never a difference
+// of two nearly equal FP32 log-means):
+//  - both pairs in the series range, L = s g(u)/2 with g(u) = f/atanh f:
 //    L - L_r = (s - s_r) g(u)/2 + s_r (g(u) - g(u_r))/2,
-//    g(u) - g(u_r) = -(u - u_r) [1/3 + 4(u+u_r)/45 + 44(u^2+u u_r+u_r^2)/945],
+//    g(u) - g(u_r) = -(u - u_r) [GF1 + GF2 (u + u_r) + ...],
 //    u - u_r = (f - f_r)(f + f_r),  f - f_r = (d' s_r - d_r s') / (s s_r);
-//  - both pairs in the log branch: with l = [[ln rho]], l_r = [[ln rho_r]]
+//  - both pairs in the log range: with l = [[ln rho]], l_r = [[ln rho_r]]
 //    and l' = l - l_r = [[ln(1 + x)]], x = rho'/rho_r,
 //    L - L_r = (d + d')/(l_r + l') - d_r/l_r = (d' l_r - d_r l') / (l l_r),
 //    whose numerator holds only perturbation-sized products; l' is one
 //    log1p of the relative jump (x_b - x_a)/(1 + x_a), l comes from the
-//    per-node logs of rho and l_r = l - l' (|l|, |l_r| >= 0.2 outside the
-//    series range);
-//  - one pair in each branch (a perturbation as large as the reference's
-//    own variation over the pair): FP64.
-// At N = 5 the kernel holds 250 of the 256 registers that keep two waves per
-// SIMD, and the FP32 log-branch form's per-node temporaries would cost it a
-// wave: there both log-branch cases take the FP64 form.
-template <int NQ>
-constexpr bool fp32_log_branch()
-{
-    return NQ != 6;
-}
-
-template <int NQ>
-__device__ __forceinline__ float dlog_mean_f(const NodeF &a, const NodeF &b)
+//    per-node logs of rho and l_r = l - l'.
+// Series form (both log-means in the series range), to u^4:
+//   L - L_r = [s' g(u) - s_r (u - u_r) h] / 2,
+//   h = GF1 + GF2 (u + u_r) + GF3 (u^2 + u u_r + u_r^2)
+//       + GF4 (u^3 + u^2 u_r + u u_r^2 + u_r^3).
+__device__ __forceinline__ float dlog_mean_series_f(const NodeF &a, const NodeF &b)
 {
     const float dr = b.rr - a.rr, sr = a.rr + b.rr;
     const float dp = b.rp - a.rp, sp = a.rp + b.rp;
     const float d = dr + dp, s = sr + sp;
-    const bool ser = fabsf(d) < LMF_SQRT * s, ser_r = fabsf(dr) < LMF_SQRT * sr;
-    if (fp32_log_branch<NQ>() && !ser && !ser_r) {
+    const float rs = rcpf(s), rsr = rcpf(sr);
+    const float f = d * rs, fr = dr * rsr;
+    const float u = f * f, ur = fr * fr;
+    const float df = (dp * sr - dr * sp) * rs * rsr;
+    const float du = df * (f + fr);
+    const float u2 = u * u + u * ur + ur * ur;
+    const float h = GF1 + (GF2 * (u + ur) + (GF3 * u2 + GF4 * (u + ur) * (u * u + ur * ur)));
+    return 0.5f * (sp * gser(u) - sr * du * h);
+}
+
+// {{rho}}_log - {{rho_r}}_log for a pair, chosen by the spreads f = |[[rho]]|/(2{{rho}})
+// and f_r of the full and the reference density:
+//  - both below 0.2: the series form (u, u_r < 0.04, where the u^4 series is
+//    exact to FP32 rounding);
+//  - otherwise, both at least 0.1: the log form;
+//  - otherwise (one spread below 0.1, the other at least 0.2: a perturbation
+//    as large as the reference's own variation over the pair): the plain
+//    difference of the two FP32 log-means, which is then itself of the size
+//    of the log-means, so that its rounding stays near eps32 relative.
+// la, lb are the per-node ln rho of the two nodes.
+constexpr float DLM_SER = 0.2f, DLM_LOG = 0.1f;
+
+__device__ __forceinline__ float dlog_mean_f(const NodeF &a, const NodeF &b, float la, float lb)
+{
+    const float dr = b.rr - a.rr, sr = a.rr + b.rr;
+    const float dp = b.rp - a.rp, sp = a.rp + b.rp;
+    const float d = dr + dp, s = sr + sp;
+    const float ad = fabsf(d), adr = fabsf(dr);
+    if (ad < DLM_SER * s && adr < DLM_SER * sr) return dlog_mean_series_f(a, b);
+    if (ad >= DLM_LOG * s && adr >= DLM_LOG * sr) {
         const float xa = a.rp * rcpf(a.rr), xb = b.rp * rcpf(b.rr);
         const float y = (xb - xa) * rcpf(1.0f + xa);
         // ln(1 + y) to a few ulp also for small y: the rounding of 1 + y is
         // undone by the factor y / ((1 + y) - 1)
         const float u1 = 1.0f + y;
         const float lp = (u1 == 1.0f) ? y : lnf(u1) * (y * rcpf(u1 - 1.0f));
-        const float l = b.lr - a.lr;
+        const float l = lb - la;
         const float l_r = l - lp;
         return (dp * l_r - dr * lp) * rcpf(l * l_r);
     }
-    if (ser && ser_r) {
-        const float rs = rcpf(s), rsr = rcpf(sr);
-        const float f = d * rs, fr = dr * rsr;
-        const float u = f * f, ur = fr * fr;
-        const float df = (dp * sr - dr * sp) * rs * rsr;
-        const float du = df * (f + fr);
-        const float h = GF1 + (GF2 * (u + ur) + GF3 * (u * u + u * ur + ur * ur));
-        return 0.5f * (sp * gser(u) - sr * du * h);
-    }
-    const double ra = (double)a.rr + (double)a.rp, rb = (double)b.rr + (double)b.rp;
-    const double l = (rb - ra) / (log(rb) - log(ra));
-    const double lr = (b.rr == a.rr) ? (double)a.rr
-                                     : ((double)b.rr - (double)a.rr) /
-                                           (log((double)b.rr) - log((double)a.rr));
-    return (float)(l - lr);
+    return log_mean_f(a.r, b.r, la, lb) - log_mean_f(a.rr, b.rr, lnf(a.rr), lnf(b.rr));
 }
 
 // Node primitives: FP64 pressure and perturbations, FP32 storage.
 __device__ __forceinline__ NodeF primitives_mixed(const Cons &c, double phi, double gm1,
-                                                  float rr_f, float pr_f, float zscale)
+                                                  float rr_f, float pr_f)
 {
     NodeF n;
     const double r = c.v[0];
@@ -168,23 +212,17 @@ __device__ __forceinline__ NodeF primitives_mixed(const Cons &c, double phi, dou
     n.z = zf;
     n.zi = (float)(p * ri);
     n.zr = rr_f * rcpf(pr_f);
-    n.izr = pr_f * rcpf(rr_f);
     // beta = b/b_r - 1 = (rho p_r)/(rho_r p) - 1 = (rho' p_r - rho_r p')/(rho_r p)
     n.beta = (float)(fdiv(rp * pr - rr * pp, rr * p));
-    n.ib1 = rcpf(1.0f + n.beta);
-    n.lr = lnf(n.r);
-    n.lz = lnf(zf * zscale);
     return n;
 }
 
 // Symmetric part of the two-point flux (FP32) with the perturbation
-// pressure in the normal momentum.  Returns {{rho}}_log.
+// pressure in the normal momentum, from the two log-means.
 template <int R>
-__device__ __forceinline__ float sym_flux_mixed(const NodeF &a, const NodeF &b, float phi_m,
-                                                float gm1i, float zscale, float S[5])
+__device__ __forceinline__ void sym_flux_f(const NodeF &a, const NodeF &b, float rho_ln,
+                                           float izln, float phi_m, float gm1i, float S[5])
 {
-    const float rho_ln = log_mean_f(a.r, b.r, a.lr, b.lr);
-    const float izln = inv_log_mean_f(a.z, b.z, a.lz, b.lz);
     const float hRa = hcompf<R>(a), hRb = hcompf<R>(b);
     const float frho = rho_ln * (hRa + hRb);
     S[0] = frho;
@@ -195,7 +233,6 @@ __device__ __forceinline__ float sym_flux_mixed(const NodeF &a, const NodeF &b, 
     const float hh = a.h0 * b.h0 + a.h1 * b.h1 + a.h2 * b.h2;
     const float cross = a.hp * hRb + b.hp * hRa;
     S[4] = frho * (izln * gm1i + 2.0f * hh + phi_m) + 2.0f * cross;
-    return rho_ln;
 }
 
 // Matrix dissipation (FP32), the operator of matrix_dissipation() with the
@@ -282,9 +319,28 @@ __device__ __forceinline__ void face_flux_mixed(const NodeF &a, const Cons &qm, 
     const double gm1 = P.gamma - 1.0;
     const float g = (float)P.gamma, gm1i = (float)P.gm1i;
     const float zscale = (float)P.lnz_scale;
-    const NodeF b = primitives_mixed(qp, phi, gm1, rr_f, pr_f, zscale);
-    const float rho_ln = log_mean_f(a.r, b.r, a.lr, b.lr);
-    const float izln = inv_log_mean_f(a.z, b.z, a.lz, b.lz);
+    const NodeF b = primitives_mixed(qp, phi, gm1, rr_f, pr_f);
+    float rho_ln, izln;
+    {
+        const float d = b.r - a.r, sm = a.r + b.r;
+        float den = sm;
+        if (!(fabsf(d) < LMF_SQRT * sm)) den = lnf(b.r) - lnf(a.r);
+        const float x = d * rcpf(den);
+        rho_ln = (fabsf(d) < LMF_SQRT * sm) ? 0.5f * sm * gser(x * x) : x;
+    }
+    {
+        const float d = b.z - a.z, sm = a.z + b.z;
+        const bool ser = fabsf(d) < LMF_SQRT * sm;
+        float num = 1.0f, den = sm;
+        if (!ser) {
+            num = lnf(b.z * zscale) - lnf(a.z * zscale);
+            den = d;
+        }
+        const float r = num * rcpf(den);
+        const float f = d * r;
+        const float u = f * f;
+        izln = ser ? 2.0f * r * (1.0f + u * (IF1 + u * (IF2 + u * (IF3 + u * IF4)))) : r;
+    }
     const float hRa = hcompf<R>(a), hRb = hcompf<R>(b);
     const float frho = rho_ln * (hRa + hRb);
     float S[5];
@@ -323,10 +379,67 @@ __device__ __forceinline__ void load_ref(const MixedParams &M, int64_t e, int n,
     pr = M.ref_p[e * NQ3 + n];
 }
 
+// Waves per SIMD the mixed kernel is compiled for: from N = 6 on, two waves
+// with a few spilled registers beat one wave without spills.
+template <int NQ>
+constexpr int mixed_min_waves()
+{
+    return NQ >= 7 ? 2 : 1;
+}
+
+// Whether the z phase of the mixed kernel holds its line's FP64 states in
+// registers for the finish (else the finish reads them again).
+template <int NQ>
+constexpr bool mixed_holds_states()
+{
+    return NQ < 6;
+}
+
+// Geopotential at LGL level k of an element spanning [zl, zr] in z.
+__device__ __forceinline__ double phi_level(const StageParams &P, const OrderTables &tb,
+                                            double zl, double zr, int k)
+{
+    const double s = tb.xi[k];
+    return P.grav * (0.5 * (1.0 - s) * zl + 0.5 * (1.0 + s) * zr);
+}
+
+// Accumulates the symmetric-flux shares of one pair (a, b) of a line.
+__device__ __forceinline__ void flux_shares_f(float tab, float tba, const float S[5],
+                                              float acc_a[5], float acc_b[5])
+{
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        acc_a[v] -= tab * S[v];
+        acc_b[v] -= tba * S[v];
+    }
+}
+
+// Accumulates the shares of one z-line pair (a, b) in the deviation of the
+// gravity term from the reference's,
+//   G - G_r = [[phi]]/4 [(B - B_r) L + (1 + B_r)(L - L_r)],
+//   B = z_b/z_a, B_r = z_r,b/z_r,a, L = {{rho}}_log,
+//   B - B_r = z_r,b (beta_b - beta_a) / z_a   (z = z_r (1 + beta)),
+// and for the partner a and b exchanged with [[phi]] negated.
+__device__ __forceinline__ void gravity_shares_f(const NodeF &na, const NodeF &nb, float tab,
+                                                 float tba, float rho_ln, float dL, float dphi,
+                                                 float &acc_a, float &acc_b)
+{
+    const float dbeta = nb.beta - na.beta;
+    const float dB = nb.zr * dbeta * na.zi;
+    const float dBi = -(na.zr * dbeta * nb.zi);
+    // 1/z_r = (1 + beta)/z
+    const float izr_a = fmaf(na.beta, na.zi, na.zi), izr_b = fmaf(nb.beta, nb.zi, nb.zi);
+    const float drh_ab = dB * rho_ln + (1.0f + nb.zr * izr_a) * dL;
+    const float drh_ba = dBi * rho_ln + (1.0f + na.zr * izr_b) * dL;
+    const float q = 0.25f * dphi;
+    acc_a -= tab * (q * drh_ab);
+    acc_b += tba * (q * drh_ba);
+}
+
 template <int NQ, int R, bool KEEP = false>
 __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const OrderTables &tb,
-                                                 int m, int64_t e, const int ec[3],
-                                                 const double phi_k[NQ], float acc[NQ][5],
+                                                 int m, int64_t e, const int ec[3], double zl,
+                                                 double zr, float acc[NQ][5],
                                                  double (*qkeep)[5] = nullptr)
 {
     constexpr int NQ3 = NQ * NQ * NQ;
@@ -335,10 +448,8 @@ __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const Ord
     const float gm1i = (float)P.gm1i;
     const float zscale = (float)P.lnz_scale;
     const double *__restrict__ qin = P.q_in;
-#pragma unroll
-    for (int a = 0; a < NQ; ++a)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) acc[a][v] = 0.0f;
+    // geopotential of node t of the line (constant along x- and y-lines)
+    auto phi = [&](int t) -> double { return phi_level(P, tb, zl, zr, R == 2 ? t : m / NQ); };
 
     Cons qc[NQ];
     float rrf[NQ], prf[NQ];
@@ -363,58 +474,87 @@ __device__ __forceinline__ void line_terms_mixed(const MixedParams &M, const Ord
     }
     NodeF nd[NQ];
 #pragma unroll
-    for (int t = 0; t < NQ; ++t)
-        nd[t] = primitives_mixed(qc[t], R == 2 ? phi_k[t] : phi_k[0], gm1, rrf[t], prf[t],
-                                 zscale);
+    for (int t = 0; t < NQ; ++t) nd[t] = primitives_mixed(qc[t], phi(t), gm1, rrf[t], prf[t]);
 
+#pragma unroll
+    for (int a = 0; a < NQ; ++a)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[a][v] = 0.0f;
     // face terms first: the conservative states die before the pair loop
     if (faces) {
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int t = side ? NQ - 1 : 0;
             float Fn[5];
-            face_flux_mixed<R>(nd[t], qc[t], qp[side], R == 2 ? phi_k[t] : phi_k[0],
-                               side ? 1.0 : -1.0, P, rrf[t], prf[t], Fn);
+            face_flux_mixed<R>(nd[t], qc[t], qp[side], phi(t), side ? 1.0 : -1.0, P, rrf[t],
+                               prf[t], Fn);
             const float wi = tb.winvf[t];
 #pragma unroll
             for (int v = 0; v < 5; ++v) acc[t][v] -= wi * Fn[v];
         }
     }
+    if (!(P.mask & TERM_VOL)) return;
 
-    if (P.mask & TERM_VOL) {
+    float phf[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) phf[t] = (float)phi(t);
+    float xr[NQ], xz[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+        xr[t] = nd[t].r;
+        xz[t] = nd[t].z;
+    }
+    const bool need_r = line_spread_f<NQ>(xr), need_z = line_spread_f<NQ>(xz);
+    // x- and y-lines take a wave-uniform series-only loop when no line of the
+    // wave can reach the log branch of either log-mean; z-lines, which also
+    // carry the gravity deviation, take the general loop
+    if (R != 2 && __ballot(need_r || need_z) == 0) {
 #pragma unroll
         for (int a = 0; a < NQ; ++a) {
 #pragma unroll
             for (int b = a + 1; b < NQ; ++b) {
-                const float phi_m = (float)(R == 2 ? 0.5 * (phi_k[a] + phi_k[b]) : phi_k[0]);
+                const float rho_ln = log_mean_series_f(nd[a].r, nd[b].r);
+                const float izln = inv_log_mean_series_f(nd[a].z, nd[b].z);
+                const float phi_m = R == 2 ? 0.5f * (phf[a] + phf[b]) : phf[0];
                 float S[5];
-                const float rho_ln = sym_flux_mixed<R>(nd[a], nd[b], phi_m, gm1i, zscale, S);
-                const float tab = tb.Tf[a][b], tba = tb.Tf[b][a];
+                sym_flux_f<R>(nd[a], nd[b], rho_ln, izln, phi_m, gm1i, S);
+                flux_shares_f(tb.Tf[a][b], tb.Tf[b][a], S, acc[a], acc[b]);
+            }
+        }
+    } else {
+        float lr[NQ], lz[NQ];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    acc[a][v] -= tab * S[v];
-                    acc[b][v] -= tba * S[v];
-                }
-                if (R == 2) {
-                    // G - G_r with rho_hat_ab = (1 + B) L / 2, B = b_b/b_a = z_b/z_a:
-                    // rho_hat - rho_hat_r = [(B - B_r) L + (1 + B_r)(L - L_r)] / 2,
-                    // B - B_r = B_r (beta_b - beta_a)/(1 + beta_a); partner likewise
-                    // with a and b exchanged and [[phi]] negated.
-                    const float dphi = (float)(phi_k[b] - phi_k[a]);
-                    const float dL = dlog_mean_f<NQ>(nd[a], nd[b]);
-                    const float Br = nd[b].zr * nd[a].izr;
-                    const float Bri = nd[a].zr * nd[b].izr;
-                    const float dB = Br * (nd[b].beta - nd[a].beta) * nd[a].ib1;
-                    const float dBi = Bri * (nd[a].beta - nd[b].beta) * nd[b].ib1;
-                    const float drh_ab = 0.5f * (dB * rho_ln + (1.0f + Br) * dL);
-                    const float drh_ba = 0.5f * (dBi * rho_ln + (1.0f + Bri) * dL);
-                    acc[a][3] -= tab * (0.5f * drh_ab * dphi);
-                    acc[b][3] -= tba * (-0.5f * drh_ba * dphi);
+        for (int t = 0; t < NQ; ++t) {
+            lr[t] = lnf(nd[t].r);
+            lz[t] = lnf(nd[t].z * zscale);
+        }
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+#pragma unroll
+            for (int b = a + 1; b < NQ; ++b) {
+                const float rho_ln = log_mean_f(nd[a].r, nd[b].r, lr[a], lr[b]);
+                const float izln = inv_log_mean_f(nd[a].z, nd[b].z, lz[a], lz[b]);
+                const float phi_m = R == 2 ? 0.5f * (phf[a] + phf[b]) : phf[0];
+                float S[5];
+                sym_flux_f<R>(nd[a], nd[b], rho_ln, izln, phi_m, gm1i, S);
+                flux_shares_f(tb.Tf[a][b], tb.Tf[b][a], S, acc[a], acc[b]);
+            }
+        }
+        if (R == 2) {
+            // the gravity deviation in a pass of its own: the flux-only
+            // quantities of the nodes are dead here
+#pragma unroll
+            for (int a = 0; a < NQ; ++a) {
+#pragma unroll
+                for (int b = a + 1; b < NQ; ++b) {
+                    const float rho_ln = log_mean_f(nd[a].r, nd[b].r, lr[a], lr[b]);
+                    const float dL = dlog_mean_f(nd[a], nd[b], lr[a], lr[b]);
+                    gravity_shares_f(nd[a], nd[b], tb.Tf[a][b], tb.Tf[b][a], rho_ln, dL,
+                                     phf[b] - phf[a], acc[a][3], acc[b][3]);
                 }
             }
         }
     }
-
 }
 
 template <int NQ, int EPW, int MODE>
@@ -434,27 +574,17 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
     int ec[3] = {0, 0, 0};
     int64_t e = 0;
     if (act) e = tile_element(P, it, ec);
-    double phi_k[NQ];
-    {
-        const double dz = P.zhi - P.zlo;
-        const double ZL = P.zlo + dz * ((double)ec[2] / (double)P.K[2]);
-        const double ZR = P.zlo + dz * ((double)(ec[2] + 1) / (double)P.K[2]);
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            const double s = tb.xi[k];
-            phi_k[k] = P.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
-        }
-    }
+    // vertical extent of the element (geopotential of its LGL levels)
+    const double dzb = P.zhi - P.zlo;
+    const double ZL = P.zlo + dzb * ((double)ec[2] / (double)P.K[2]);
+    const double ZR = P.zlo + dzb * ((double)(ec[2] + 1) / (double)P.K[2]);
 
     float acc[NQ][5];
     const bool vol_or_face = (P.mask & (TERM_VOL | TERM_FACE)) != 0;
 
     if (act) {
         if (vol_or_face) {
-            double phl[NQ];
-#pragma unroll
-            for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
-            line_terms_mixed<NQ, 0>(M, tb, m, e, ec, phl, acc);
+            line_terms_mixed<NQ, 0>(M, tb, m, e, ec, ZL, ZR, acc);
         } else {
 #pragma unroll
             for (int t = 0; t < NQ; ++t)
@@ -472,10 +602,7 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
     __syncthreads();
 
     if (act && vol_or_face) {
-        double phl[NQ];
-#pragma unroll
-        for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
-        line_terms_mixed<NQ, 1>(M, tb, m, e, ec, phl, acc);
+        line_terms_mixed<NQ, 1>(M, tb, m, e, ec, ZL, ZR, acc);
         const float th = (float)P.two_h[1];
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
@@ -489,95 +616,81 @@ __device__ __forceinline__ void stage_mixed_body(const MixedParams &M, int lb)
     if (!act) return;
     const int64_t base0 = e * 5 * NQ3 + m;
     const double *__restrict__ qin = P.q_in;
-    // the z line's states stay in registers for the update
-    double qv[NQ][5];
+    constexpr bool HOLD = mixed_holds_states<NQ>();
+    double qv[HOLD ? NQ : 1][5];
     if (vol_or_face) {
-        line_terms_mixed<NQ, 2, true>(M, tb, m, e, ec, phi_k, acc, qv);
+        line_terms_mixed<NQ, 2, HOLD>(M, tb, m, e, ec, ZL, ZR, acc, qv);
     } else {
 #pragma unroll
         for (int t = 0; t < NQ; ++t)
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 acc[t][v] = 0.0f;
-                qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
+                if constexpr (HOLD) qv[t][v] = qin[base0 + v * NQ3 + NQ2 * t];
             }
     }
+    auto qs = [&](int t, int v) -> double {
+        if constexpr (HOLD)
+            return qv[t][v];
+        else
+            return qin[base0 + v * NQ3 + NQ2 * t];
+    };
     const bool src = (P.mask & TERM_SRC) != 0;
     // the reference part R(q_r) belongs to the pressure-gravity terms
     const bool with_ref = (P.mask & (TERM_VOL | TERM_FACE)) == (TERM_VOL | TERM_FACE);
-    float rrm[NQ][3];
+    const float th = (float)P.two_h[2];
+    constexpr bool nts = NQ >= NT_STAGE_MIN_NQ;
+    // the first LSRK stage (A = 0) does not read dq
+    const bool use_dq = MODE == MODE_STAGE && P.A != 0.0;
+    double *__restrict__ rout = P.r_out;
+    double *__restrict__ dqp = P.dq;
+    double *__restrict__ qout = P.q_out;
+    bool bad = false;
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
+        const int n = m + NQ2 * t;
+        const int64_t o = base0 + NQ2 * t;
+        double qn[5];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            rrm[t][c] = with_ref ? M.rr_mom[(e * 3 + c) * NQ3 + m + NQ2 * t] : 0.0f;
-    }
-    const float th = (float)P.two_h[2];
-    if (MODE == MODE_RHS) {
-        double *__restrict__ rout = P.r_out;
+        for (int v = 0; v < 5; ++v) qn[v] = qs(t, v);
+        double Rv[5];
 #pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-            const int n = m + NQ2 * t;
-            double Rv[5];
+        for (int v = 0; v < 5; ++v) Rv[v] = (double)(sacc[v][el][n] + th * acc[t][v]);
+        if (with_ref) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) Rv[v] = (double)(sacc[v][el][n] + th * acc[t][v]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Rv[1 + c] += (double)rrm[t][c];
-            if (src) {
-                Rv[1] += P.cor_f * qv[t][2];
-                Rv[2] -= P.cor_f * qv[t][1];
-            }
-#pragma unroll
-            for (int v = 0; v < 5; ++v) store_f64<true>(&rout[base0 + v * NQ3 + NQ2 * t], Rv[v]);
+            for (int c = 0; c < 3; ++c) Rv[1 + c] += (double)M.rr_mom[(e * 3 + c) * NQ3 + n];
         }
-    } else {
-        double *__restrict__ dqp = P.dq;
-        double *__restrict__ qout = P.q_out;
-        constexpr bool nts = NQ >= NT_STAGE_MIN_NQ;
-        // the first LSRK stage (A = 0) does not read dq
-        const bool use_dq = P.A != 0.0;
-        double dv[NQ][5];
-        if (use_dq) {
-#pragma unroll
-            for (int t = 0; t < NQ; ++t)
-#pragma unroll
-                for (int v = 0; v < 5; ++v) dv[t][v] = load_f64<nts>(&dqp[base0 + v * NQ3 + NQ2 * t]);
+        if (src) {
+            Rv[1] += P.cor_f * qn[2];
+            Rv[2] -= P.cor_f * qn[1];
         }
+        if (MODE == MODE_RHS) {
 #pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-            const int n = m + NQ2 * t;
-            double Rv[5];
+            for (int v = 0; v < 5; ++v) store_f64<true>(&rout[o + v * NQ3], Rv[v]);
+        } else {
+            double dv[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) Rv[v] = (double)(sacc[v][el][n] + th * acc[t][v]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Rv[1 + c] += (double)rrm[t][c];
-            if (src) {
-                Rv[1] += P.cor_f * qv[t][2];
-                Rv[2] -= P.cor_f * qv[t][1];
-            }
+            for (int v = 0; v < 5; ++v) dv[v] = use_dq ? load_f64<nts>(&dqp[o + v * NQ3]) : 0.0;
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double d = use_dq ? P.A * dv[t][v] + P.dt * Rv[v] : P.dt * Rv[v];
-                store_f64<nts>(&dqp[base0 + v * NQ3 + NQ2 * t], d);
-                store_f64<nts>(&qout[base0 + v * NQ3 + NQ2 * t], qv[t][v] + P.B * d);
+                const double d = use_dq ? P.A * dv[v] + P.dt * Rv[v] : P.dt * Rv[v];
+                store_f64<nts>(&dqp[o + v * NQ3], d);
+                store_f64<nts>(&qout[o + v * NQ3], qn[v] + P.B * d);
             }
         }
-    }
-    if (P.flag) {
-        bool bad = false;
-#pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-            const double r = qv[t][0];
-            const double kin = qv[t][1] * qv[t][1] + qv[t][2] * qv[t][2] + qv[t][3] * qv[t][3];
-            const double eint = qv[t][4] - 0.5 * kin / r - r * phi_k[t];
+        if (P.flag) {
+            const double r = qn[0];
+            const double kin = qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3];
+            const double eint = qn[4] - 0.5 * kin / r - r * phi_level(P, tb, ZL, ZR, t);
             bad |= !(r > 0.0) || !(eint > 0.0);
         }
-        if (bad) atomicOr(P.flag, 1);
     }
+    if (P.flag && bad) atomicOr(P.flag, 1);
 }
 
 template <int NQ, int EPW, int MODE>
-__global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_mixed(const MixedParams M)
+__global__ void __launch_bounds__((block_threads<NQ, EPW>()), (mixed_min_waves<NQ>()))
+    stage_mixed(const MixedParams M)
 {
     stage_mixed_body<NQ, EPW, MODE>(M, xcd_remap(blockIdx.x, M.s.nblocks));
 }
@@ -600,7 +713,7 @@ struct PackLaunchMixed {
 };
 
 template <int NQ, int EPW, int MODE>
-__global__ void __launch_bounds__((block_threads<NQ, EPW>()))
+__global__ void __launch_bounds__((block_threads<NQ, EPW>()), (mixed_min_waves<NQ>()))
     stage_mixed_packed(const PackLaunchMixed L)
 {
     const int gb = xcd_remap(blockIdx.x, L.nblocks);
