@@ -256,6 +256,17 @@ int esdg_pack_step(esdg_pack_t pack, int32_t nsteps);
  * members' states are unaffected by a failing one (members share no data). */
 int esdg_pack_flags(esdg_pack_t pack, int32_t *out);
 
+/* esdg_pack_flags without synchronising: enqueues on the pack's stream the
+ * gathering (and clearing) of every member's flag into out_host[i] (nonzero:
+ * member i met rho <= 0, p <= 0 or NaN since its flag was last read).  The
+ * values are there once the stream has passed this call (e.g. when an event
+ * recorded after it has completed); out_host must hold n int32 of host
+ * memory and stay valid until then, and should be pinned (hipHostMalloc),
+ * since a copy into pageable memory may complete synchronously.  For a
+ * serving loop that must not block on a bucket whose stream queues behind
+ * other streams' launches. */
+int esdg_pack_flags_async(esdg_pack_t pack, int32_t *out_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1350,4 +1350,20 @@ int esdg_pack_flags(esdg_pack_t p, int32_t *out)
     return ESDG_OK;
 }
 
+int esdg_pack_flags_async(esdg_pack_t p, int32_t *out_host)
+{
+    if (!p) return fail(ESDG_EINVAL, "NULL pack");
+    if (!out_host) return fail(ESDG_EINVAL, "out_host is NULL");
+    if (p->n < 1) return fail(ESDG_EINVAL, "pack has no members");
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) HIP_TRY(hipSetDevice(p->device));
+    hipLaunchKernelGGL(pack_flags_kernel, dim3((unsigned)((p->n + 255) / 256)), dim3(256), 0,
+                       p->stream, (int *const *)p->d_flagptrs, p->n, p->d_flags);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out_host, p->d_flags, sizeof(int) * p->n, hipMemcpyDeviceToHost,
+                           p->stream));
+    return ESDG_OK;
+}
+
 }  // extern "C"

@@ -636,12 +636,23 @@ constexpr int block_threads()
 // At N=5 and N=6 reading them again in the finish fits two waves per SIMD
 // without spills, where holding them costs half the occupancy (2.5-16% and
 // 11% faster steps); at N=7 and N=8 reading them again does not reach two
-// waves (forcing two waves spills 260 B per lane at N=7) and was slower; up
-// to N=4 the kernel fits two waves either way.
-template <int NQ>
+// waves (forcing two waves spills 260 B per lane at N=7) and was slower for
+// stage launches; up to N=4 the kernel fits two waves either way, and
+// holding saves the second read (the RHS launch at N=4 is 16% slower
+// without).  The N=7 RHS launch reads them again and runs two waves (below).
+template <int NQ, int MODE>
 constexpr bool stage_holds_states()
 {
-    return NQ != 6 && NQ != 7;
+    return NQ != 6 && NQ != 7 && !(MODE == MODE_RHS && NQ == 8);
+}
+
+// Waves per SIMD a launch is compiled for (1: the compiler's choice).  The
+// N=7 RHS launch runs two waves with 284 B of spills per lane, 8% faster
+// than one wave without; the N=7 stage launch was 4% slower that way.
+template <int NQ, int MODE>
+constexpr int stage_min_waves()
+{
+    return (MODE == MODE_RHS && NQ == 8) ? 2 : 1;
 }
 
 // One workgroup handles EPW elements (logical block lb of the mesh); lane
@@ -723,7 +734,7 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     const bool src = (P.mask & TERM_SRC) != 0;
     // the z line's states stay in registers for the update (HOLD), or the
     // finish reads them again
-    constexpr bool HOLD = stage_holds_states<NQ>();
+    constexpr bool HOLD = stage_holds_states<NQ, MODE>();
     const double *__restrict__ qin = P.q_in;
     double qv[HOLD ? NQ : 1][5];
     if (vol_or_face) {
@@ -806,7 +817,8 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
 }
 
 template <int NQ, int EPW, int MODE>
-__global__ void __launch_bounds__((block_threads<NQ, EPW>())) stage_fp64(const StageParams P)
+__global__ void __launch_bounds__((block_threads<NQ, EPW>()), (stage_min_waves<NQ, MODE>()))
+    stage_fp64(const StageParams P)
 {
     stage_body<NQ, EPW, MODE>(P, xcd_remap(blockIdx.x, P.nblocks));
 }

@@ -87,6 +87,7 @@ SIGNATURES = {
                                         C.POINTER(C.c_void_p), _dp, C.POINTER(C.c_int32)]),
     "esdg_pack_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "esdg_pack_flags": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "esdg_pack_flags_async": (C.c_int, [C.c_void_p, C.c_void_p]),
 }
 
 
@@ -340,3 +341,14 @@ class Pack:
         buf = (C.c_int32 * max(self.n, 1))()
         _check(lib.esdg_pack_flags(self._h, buf))
         return [bool(buf[i]) for i in range(self.n)]
+
+    def flags_async(self, out):
+        """Enqueue the flag gathering into `out`, a pinned host int32 torch
+        tensor of at least n entries, on the pack's stream (no
+        synchronisation): out[:n] holds the flags once the stream has passed
+        this call."""
+        torch = _torch()
+        if not (isinstance(out, torch.Tensor) and out.dtype == torch.int32 and not out.is_cuda
+                and out.is_contiguous() and out.numel() >= self.n):
+            raise ValueError("out must be a contiguous host int32 tensor of at least n entries")
+        _check(lib.esdg_pack_flags_async(self._h, C.c_void_p(out.data_ptr())))

@@ -272,6 +272,11 @@ class GpuExecutor:
                                   [h["bufs"][1] for h in hs], [h["dq"] for h in hs],
                                   [h["dt"] for h in hs], [h["parity"] for h in hs])
         b["members"] = list(members)
+        # pinned host buffer that each step's flags are copied into (the
+        # copy is enqueued behind the step, so reading it needs no sync)
+        if b.get("hflags") is None or b["hflags"].numel() < len(members):
+            b["hflags"] = torch.zeros(max(8, 2 * len(members)), dtype=torch.int32,
+                                      pin_memory=True)
         self.times["set_members_s"] += time.perf_counter() - t0
 
     def drop_bucket(self, key):
@@ -287,6 +292,7 @@ class GpuExecutor:
             ev0 = torch.cuda.Event(enable_timing=True)
             ev0.record(b["stream"])
             b["pack"].step(1)  # the first step after set_members captures the graph
+            b["pack"].flags_async(b["hflags"])
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(b["stream"])
         for mb in b["members"]:
@@ -297,13 +303,14 @@ class GpuExecutor:
 
     def failed_members(self, key) -> List[Member]:
         """Members of the bucket's completed step whose own non-physical flag
-        is set (the flags are cleared)."""
+        is set (the flags were gathered, and cleared, behind the step; its
+        completion event covers the copy, so nothing waits here)."""
         t0 = time.perf_counter()
         b = self.buckets[key]
         if b.get("ev_start") is not None:
             self.times["device_step_s"] += b["ev_start"].elapsed_time(b["ev_done"]) * 1e-3 \
                 if b.get("ev_done") is not None else 0.0
-        flags = b["pack"].flags()
+        flags = b["hflags"][:len(b["members"])].tolist()
         self.times["flag_reads_s"] += time.perf_counter() - t0
         return [mb for mb, f in zip(b["members"], flags) if f]
 

@@ -129,3 +129,35 @@ def test_pack_table_grows_and_shrinks():
         for i, b in zip(sel, bufs):
             assert torch.equal(b[0], built[i][3]), (sel, i)   # 2 steps: back in buffer 0
     pack.close()
+
+
+def test_async_flag_gathering_matches_the_synchronous_read():
+    from paper_2605_16684_amd import esdg
+    reqs = [S.Request(0, "bubble", (2, 2, 2), 4, S.FP64, 1, 1),
+            S.Request(1, "bubble", (3, 2, 2), 4, S.FP64, 2, 1),
+            S.Request(2, "bubble", (2, 3, 2), 4, S.FP64, 3, 1)]
+    members = []
+    for r in reqs:
+        m, q, _ = S._make_member_mesh(r)
+        dt = m.cfl_dt(q, 0.5)
+        members.append((m, q, torch.empty_like(q), torch.zeros_like(q), dt))
+    members[1][1][3, 0, 7] = -1.0   # one node of member 1 with rho < 0
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())  # the states were written there
+    pack = esdg.Pack(stream)
+    pack.set_members([x[0] for x in members], [x[1] for x in members], [x[2] for x in members],
+                     [x[3] for x in members], [x[4] for x in members], [0, 0, 0])
+    host = torch.full((8,), -7, dtype=torch.int32, pin_memory=True)
+    with torch.cuda.stream(stream):
+        pack.step(1)
+        pack.flags_async(host)
+        ev = torch.cuda.Event()
+        ev.record(stream)
+    ev.synchronize()
+    got = [bool(x) for x in host[:3].tolist()]
+    assert got == [False, True, False]
+    assert host[3:].tolist() == [-7] * 5          # nothing written beyond n
+    assert pack.flags() == [False, False, False]  # the async read cleared them
+    with pytest.raises(ValueError):
+        pack.flags_async(torch.zeros(2, dtype=torch.int32, pin_memory=True))
+    pack.close()
