@@ -225,6 +225,12 @@ class GpuExecutor:
         # host seconds spent per activity, and device seconds of the steps
         self.times = {"admission_s": 0.0, "set_members_s": 0.0, "launch_and_capture_s": 0.0,
                       "flag_reads_s": 0.0, "release_s": 0.0, "device_step_s": 0.0}
+        # meshes of released members, destroyed in batches: destroying one
+        # synchronises its stream and frees device memory, which waits for
+        # the device, so it is done when the budget needs the bytes or when
+        # no step is in flight
+        self._retired: List[object] = []
+        self._retired_bytes = 0
 
     def now(self) -> float:
         return time.perf_counter() - self.t0_host
@@ -333,10 +339,26 @@ class GpuExecutor:
         result = None
         if self.keep_results and keep:
             result = h["bufs"][h["parity"]].cpu().numpy()
-        h["mesh"].close()
+        self._retired.append(h["mesh"])
+        self._retired_bytes += h["mesh"].footprint
         mb.handle = None
         self.times["release_s"] += time.perf_counter() - t0
         return result
+
+    def retired_bytes(self) -> int:
+        """Device bytes still held by the meshes of released members."""
+        return self._retired_bytes
+
+    def flush_retired(self):
+        """Destroy the meshes of released members."""
+        if not self._retired:
+            return
+        t0 = time.perf_counter()
+        for m in self._retired:
+            m.close()
+        self._retired = []
+        self._retired_bytes = 0
+        self.times["release_s"] += time.perf_counter() - t0
 
 
 class FakeExecutor:
@@ -535,6 +557,8 @@ class Server:
         failed: List[Member] = []
         steps_launched = max_conc = 0
         buckets_seen = set()
+        retired = getattr(ex, "retired_bytes", lambda: 0)
+        flush = getattr(ex, "flush_retired", lambda: None)
         inflight: Dict[tuple, object] = {}      # bucket -> completion token of its step
         stepping: Dict[tuple, List[Member]] = {}  # bucket -> members of that step
         t_start = ex.now()
@@ -551,6 +575,8 @@ class Server:
                 fp = footprint_bytes(r)
                 if used + fp > self.budget:
                     continue
+                if used + retired() + fp > self.budget:
+                    flush()
                 try:
                     handle, t_adm = ex.admit(r)
                 except Exception:
@@ -583,6 +609,7 @@ class Server:
                     stepping[key] = list(ms)  # members admitted later join after this step
                     steps_launched += 1
             if not inflight:
+                flush()
                 if not pending and not queue:
                     break
                 if pending:
@@ -627,6 +654,7 @@ class Server:
                         dirty.add(key)
         for key in list(active):
             ex.drop_bucket(key)
+        flush()
         makespan = max((mb.finished for mb in done), default=0.0)
         first = min((r.arrival for r in requests), default=0.0)
         span = max(makespan - first, 1e-12)
