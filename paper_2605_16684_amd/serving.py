@@ -368,7 +368,7 @@ class FakeExecutor:
     the CUs).  Time is virtual."""
 
     def __init__(self, cost_per_node=None, overhead=20e-6, admit_cost=1e-3, fail_on=None,
-                 nonphysical_on=None):
+                 nonphysical_on=None, retire_fraction=0.0):
         self.cost = cost_per_node or (lambda N, prec: 5 * 1e-10 * (1.0 if prec == FP64 else 0.8))
         self.overhead = overhead
         self.admit_cost = admit_cost
@@ -380,6 +380,12 @@ class FakeExecutor:
         # request id -> step (1-based) after which its flag reads non-physical
         self.nonphysical_on = dict(nonphysical_on or {})
         self.times = {}
+        # device bytes: live members, and the part of released members'
+        # footprints (retire_fraction) held until flush_retired, as the GPU
+        # executor holds released meshes; peak_bytes is their largest sum
+        self.retire_fraction = retire_fraction
+        self.live_bytes = self.retired = self.peak_bytes = 0
+        self.flushes = 0
 
     def now(self) -> float:
         return self.clock
@@ -409,6 +415,8 @@ class FakeExecutor:
         if req.rid in self.fail_on:
             raise RuntimeError(f"simulated failure admitting request {req.rid}")
         self._run_until(self.clock + self.admit_cost)
+        self.live_bytes += footprint_bytes(req)
+        self.peak_bytes = max(self.peak_bytes, self.live_bytes + self.retired)
         return {"parity": 0}, self.clock
 
     def set_bucket(self, key, members):
@@ -442,7 +450,18 @@ class FakeExecutor:
                 and mb.steps_done + 1 >= self.nonphysical_on[mb.req.rid]]
 
     def release(self, mb, keep: bool = True):
+        fp = footprint_bytes(mb.req)
+        self.live_bytes -= fp
+        self.retired += int(self.retire_fraction * fp)
         return None
+
+    def retired_bytes(self) -> int:
+        return self.retired
+
+    def flush_retired(self):
+        if self.retired:
+            self.flushes += 1
+        self.retired = 0
 
 
 # ---------------------------------------------------------------------------

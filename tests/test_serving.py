@@ -158,3 +158,18 @@ def test_footprint_formula():
     assert S.footprint_bytes(r) >= 120 * r.nodes
     rm = S.Request(0, "bubble", (10, 10, 10), 4, S.FP32_MIXED, 0, 1)
     assert S.footprint_bytes(rm) - S.footprint_bytes(r) == 20 * r.nodes
+
+
+def test_released_members_memory_is_counted_until_flushed():
+    # released members keep part of their device memory (their meshes) until
+    # the executor destroys them in a batch: admission must count it and
+    # flush when a request would not fit otherwise
+    reqs = S.request_stream(n=40, seed=5, mean_interarrival=1e-4, steps=3, kmin=2, kmax=8)
+    budget = max(int(0.3 * sum(S.footprint_bytes(r) for r in reqs)),
+                 max(S.footprint_bytes(r) for r in reqs))
+    ex = S.FakeExecutor(retire_fraction=0.5)
+    st = S.Server(budget, executor=ex).run(reqs, realtime=False)
+    assert st.n_completed == len(reqs)
+    assert ex.flushes >= 1
+    assert ex.peak_bytes <= budget
+    assert ex.retired == 0            # everything flushed at the end
