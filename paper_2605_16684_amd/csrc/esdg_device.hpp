@@ -502,11 +502,31 @@ __device__ __forceinline__ void pair_shares(const OrderTables &tb, const Node nd
 // unscaled sums (the caller multiplies by 2/h_R).  The face terms come
 // first, so that the line's conservative states and the neighbours' die
 // before the pair loop, which holds only the primitives and the sums.
+// Geopotential at the LGL levels of an element spanning [zl, zr] in z: held
+// per node by the caller (phi_in), or formed here from the extent where
+// fewer live registers matter more (phi_from_levels).
+template <int NQ>
+constexpr bool phi_from_levels()
+{
+    return NQ == 8;
+}
+
 template <int NQ, int R, bool KEEP = false>
 __device__ __forceinline__ void line_terms(const StageParams &P, const OrderTables &tb, int m,
-                                           int64_t e, const int ec[3], const double phi_k[NQ],
-                                           double acc[NQ][5], double (*qkeep)[5] = nullptr)
+                                           int64_t e, const int ec[3], const double *phi_in,
+                                           double zl, double zr, double acc[NQ][5],
+                                           double (*qkeep)[5] = nullptr)
 {
+    double phi_k[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+        if constexpr (phi_from_levels<NQ>()) {
+            const double s = tb.xi[R == 2 ? t : m / NQ];
+            phi_k[t] = P.grav * (0.5 * (1.0 - s) * zl + 0.5 * (1.0 + s) * zr);
+        } else {
+            phi_k[t] = phi_in[t];
+        }
+    }
     constexpr int NQ3 = NQ * NQ * NQ;
     const double gm1 = P.gamma - 1.0, gm1i = P.gm1i;
     const double *__restrict__ qin = P.q_in;
@@ -635,24 +655,24 @@ constexpr int block_threads()
 // Whether the z phase holds its line's states in registers for the finish.
 // At N=5 and N=6 reading them again in the finish fits two waves per SIMD
 // without spills, where holding them costs half the occupancy (2.5-16% and
-// 11% faster steps); at N=7 and N=8 reading them again does not reach two
-// waves (forcing two waves spills 260 B per lane at N=7) and was slower for
-// stage launches; up to N=4 the kernel fits two waves either way, and
-// holding saves the second read (the RHS launch at N=4 is 16% slower
-// without).  The N=7 RHS launch reads them again and runs two waves (below).
+// 11% faster steps); at N=7 the kernel reads them again and is compiled for
+// two waves (below); at N=8 reading them again was slower (one wave either
+// way); up to N=4 the kernel fits two waves either way, and holding saves
+// the second read (the RHS launch at N=4 is 16% slower without).
 template <int NQ, int MODE>
 constexpr bool stage_holds_states()
 {
-    return NQ != 6 && NQ != 7 && !(MODE == MODE_RHS && NQ == 8);
+    return NQ != 6 && NQ != 7 && NQ != 8;
 }
 
-// Waves per SIMD a launch is compiled for (1: the compiler's choice).  The
-// N=7 RHS launch runs two waves with 284 B of spills per lane, 8% faster
-// than one wave without; the N=7 stage launch was 4% slower that way.
+// Waves per SIMD a launch is compiled for (1: the compiler's choice).  At
+// N=7, with the states read again and the geopotential formed from the
+// element's extent, two waves spill 172-180 B per lane and run 8.5% faster
+// per LSRK step and 3-8% per RHS launch than one wave with AGPR copies.
 template <int NQ, int MODE>
 constexpr int stage_min_waves()
 {
-    return (MODE == MODE_RHS && NQ == 8) ? 2 : 1;
+    return NQ == 8 ? 2 : 1;
 }
 
 // One workgroup handles EPW elements (logical block lb of the mesh); lane
@@ -675,16 +695,17 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     int64_t e = 0;
     if (act) e = tile_element(P, it, ec);
     // geopotential at the nodes of this element's z-levels
-    double phi_k[NQ];
-    {
-        const double dz = P.zhi - P.zlo;
-        const double ZL = P.zlo + dz * ((double)ec[2] / (double)P.K[2]);
-        const double ZR = P.zlo + dz * ((double)(ec[2] + 1) / (double)P.K[2]);
+    const double dzb = P.zhi - P.zlo;
+    const double ZL = P.zlo + dzb * ((double)ec[2] / (double)P.K[2]);
+    const double ZR = P.zlo + dzb * ((double)(ec[2] + 1) / (double)P.K[2]);
+    auto phi_at = [&](int k) -> double {
+        const double s = tb.xi[k];
+        return P.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
+    };
+    double phi_k[phi_from_levels<NQ>() ? 1 : NQ];
+    if constexpr (!phi_from_levels<NQ>()) {
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            const double s = tb.xi[k];
-            phi_k[k] = P.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
-        }
+        for (int k = 0; k < NQ; ++k) phi_k[k] = phi_at(k);
     }
 
     double acc[NQ][5];
@@ -696,9 +717,11 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     if (act) {
         if (vol_or_face) {
             double phl[NQ];
+            if constexpr (!phi_from_levels<NQ>()) {
 #pragma unroll
-            for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
-            line_terms<NQ, 0>(P, tb, m, e, ec, phl, acc);
+                for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
+            }
+            line_terms<NQ, 0>(P, tb, m, e, ec, phl, ZL, ZR, acc);
         } else {
 #pragma unroll
             for (int t = 0; t < NQ; ++t)
@@ -717,9 +740,11 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     // y phase: lane m = (i, k)
     if (act && vol_or_face) {
         double phl[NQ];
+        if constexpr (!phi_from_levels<NQ>()) {
 #pragma unroll
-        for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
-        line_terms<NQ, 1>(P, tb, m, e, ec, phl, acc);
+            for (int t = 0; t < NQ; ++t) phl[t] = phi_k[m / NQ];
+        }
+        line_terms<NQ, 1>(P, tb, m, e, ec, phl, ZL, ZR, acc);
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             const int n = line_node<NQ, 1>(m, t);
@@ -738,7 +763,7 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
     const double *__restrict__ qin = P.q_in;
     double qv[HOLD ? NQ : 1][5];
     if (vol_or_face) {
-        line_terms<NQ, 2, HOLD>(P, tb, m, e, ec, phi_k, acc, qv);
+        line_terms<NQ, 2, HOLD>(P, tb, m, e, ec, phi_k, ZL, ZR, acc, qv);
     } else {
 #pragma unroll
         for (int t = 0; t < NQ; ++t)
@@ -809,7 +834,8 @@ __device__ __forceinline__ void stage_body(const StageParams &P, int lb)
             const double q0 = qs(t, 0), q1 = qs(t, 1), q2 = qs(t, 2), q3 = qs(t, 3);
             const double r = q0;
             const double kin = q1 * q1 + q2 * q2 + q3 * q3;
-            const double eint = qs(t, 4) - 0.5 * kin / r - r * phi_k[t];
+            const double ph = phi_from_levels<NQ>() ? phi_at(t) : phi_k[t];
+            const double eint = qs(t, 4) - 0.5 * kin / r - r * ph;
             bad |= !(r > 0.0) || !(eint > 0.0);
         }
         if (bad) atomicOr(P.flag, 1);
@@ -856,7 +882,7 @@ __device__ __forceinline__ int pack_member(const PackLaunch &L, int gb)
 }
 
 template <int NQ, int EPW, int MODE>
-__global__ void __launch_bounds__((block_threads<NQ, EPW>()))
+__global__ void __launch_bounds__((block_threads<NQ, EPW>()), (stage_min_waves<NQ, MODE>()))
     stage_fp64_packed(const PackLaunch L)
 {
     const int gb = xcd_remap(blockIdx.x, L.nblocks);
