@@ -44,7 +44,7 @@ extern "C" {
 
 enum {
     ESDG_OK = 0,
-    ESDG_EINVAL = -1,    /* bad argument: N outside 1..8, K < 1, K[0]K[1]K[2] >= 2^31,
+    ESDG_EINVAL = -1,    /* bad argument: N outside 1..15, K < 1, K[0]K[1]K[2] >= 2^31,
                             hi <= lo, NULL/misaligned pointer, periodic z with
                             grav != 0, no compiled kernel variant */
     ESDG_ENOMEM = -2,    /* device allocation failed */
@@ -60,7 +60,13 @@ enum { ESDG_TERM_VOL = 1, ESDG_TERM_FACE = 2, ESDG_TERM_SRC = 4, ESDG_TERM_ALL =
 typedef struct esdg_mesh *esdg_mesh_t;
 
 /* Mesh description (paper Sec. 3 and the test-case geometry of Sec. 5).
- *   N            polynomial order, 1..8 (Nq = N+1 nodes per direction)
+ *   N            polynomial order, 1..15 (Nq = N+1 nodes per direction).
+ *                Orders 1..8 run the fused line-per-lane stage kernels;
+ *                orders 9..15 run a node-per-thread path (per-node
+ *                primitives, then the stage or RHS kernel: two launches,
+ *                56 B per node of device scratch held by the mesh), FP64
+ *                on the affine box only, without elements-per-workgroup
+ *                variants (epw must be 0) and not packable
  *   K[3]         elements per direction
  *   lo/hi[3]     box corners in metres
  *   periodic[3]  1 = periodic in that direction, 0 = reflecting walls
@@ -205,13 +211,14 @@ const char *esdg_version(void);
 
 /* Host-only: the library's LGL nodes xi[N+1], weights w[N+1] and
  * differentiation matrix D[(N+1)*(N+1)] (row-major, D[i][j] = l_j'(xi_i))
- * for order N in 1..8 (paper Sec. 3: collocated LGL quadrature, matrix-free
+ * for order N in 1..15 (paper Sec. 3: collocated LGL quadrature, matrix-free
  * tensor-product derivatives).  No device work; usable without a GPU. */
 int esdg_lgl_tables(int32_t N, double *xi, double *w, double *D);
 
 /* Elements-per-workgroup values compiled for order N and a precision
  * (ESDG_FP64 or ESDG_FP32_MIXED) on the affine box: writes up to cap of them
- * to out (may be NULL) and returns their count, or a negative error.
+ * to out (may be NULL) and returns their count (0 for N above 8, whose
+ * kernels have no such variants), or a negative error.
  * Curved meshes use the FP64 default of each order only.  Host-only. */
 int esdg_epw_options(int32_t N, int32_t precision, int32_t *out, int32_t cap);
 
@@ -236,7 +243,7 @@ int esdg_pack_create(void *hip_stream, esdg_pack_t *out);
 /* Synchronise the pack's stream and free it (members are not touched). */
 int esdg_pack_destroy(esdg_pack_t pack);
 
-/* Replace the member set: n meshes (same N, precision, epw, device), each
+/* Replace the member set: n meshes (same N <= 8, precision, epw, device), each
  * with q0[i], q1[i], dq[i] (device arrays of its state_len doubles, not
  * overlapping), time step dt[i], and parity[i] in {0, 1} naming the buffer
  * that holds its current state.  Synchronises the pack's stream; drops the

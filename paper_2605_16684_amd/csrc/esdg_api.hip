@@ -19,6 +19,7 @@
 #include "esdg_device.hpp"
 #include "esdg_mixed.hpp"
 #include "esdg_curved.hpp"
+#include "esdg_high.hpp"
 
 using namespace esdg;
 
@@ -200,6 +201,7 @@ struct esdg_mesh {
     int epw;
     double h[3];
     double *d_q2;        // ping-pong state
+    double *d_prim;      // N > 8: per-node primitives [e][7][n] of the stage input
     double *d_r;         // RHS scratch (entropy production)
     double *d_partials;  // reduction partials
     double *d_red_out;   // 4 doubles
@@ -430,8 +432,28 @@ int launch_stage_curved(esdg_mesh *m, StageParams P)
     return ESDG_OK;
 }
 
+// Orders above N_FUSED_MAX: primitives of the stage input, then the
+// node-per-thread stage (or RHS) kernel.
+int launch_stage_high(esdg_mesh *m, StageParams P)
+{
+    const int64_t nb = (m->nn + HIGH_THREADS - 1) / HIGH_THREADS;
+    if (nb > 0x7fffffff) return fail(ESDG_EINVAL, "mesh too large");
+    hipLaunchKernelGGL(prim_kernel, dim3((unsigned)nb), dim3(HIGH_THREADS), 0, m->stream, P, m->N,
+                       m->d_prim);
+    HIP_TRY(hipGetLastError());
+    if (P.mode == MODE_RHS)
+        hipLaunchKernelGGL(stage_high_kernel<MODE_RHS>, dim3((unsigned)nb), dim3(HIGH_THREADS), 0,
+                           m->stream, P, m->N, (const double *)m->d_prim);
+    else
+        hipLaunchKernelGGL(stage_high_kernel<MODE_STAGE>, dim3((unsigned)nb), dim3(HIGH_THREADS),
+                           0, m->stream, P, m->N, (const double *)m->d_prim);
+    HIP_TRY(hipGetLastError());
+    return ESDG_OK;
+}
+
 int launch_stage(esdg_mesh *m, StageParams P)
 {
+    if (m->N > N_FUSED_MAX) return launch_stage_high(m, P);
     if (m->curved) return launch_stage_curved(m, P);
     if (m->desc.precision != ESDG_FP32_MIXED) return launch_stage_fp64(m, P, m->epw);
     const MixedVariant *v = find_mixed_variant(m->N, m->epw);
@@ -715,7 +737,14 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
 {
     if (!d || !out) return fail(ESDG_EINVAL, "NULL argument");
     *out = nullptr;
-    if (d->N < 1 || d->N > NQ_MAX - 1) return fail(ESDG_EINVAL, "N=%d outside 1..8", d->N);
+    if (d->N < 1 || d->N > NQ_MAX - 1)
+        return fail(ESDG_EINVAL, "N=%d outside 1..%d", d->N, NQ_MAX - 1);
+    const bool high = d->N > N_FUSED_MAX;
+    if (high && (d->precision != ESDG_FP64 || d->curved))
+        return fail(ESDG_EINVAL, "orders above %d run in FP64 on the affine box only", N_FUSED_MAX);
+    if (high && d->epw != 0)
+        return fail(ESDG_EINVAL, "orders above %d have no elements-per-workgroup variants",
+                    N_FUSED_MAX);
     for (int k = 0; k < 3; ++k) {
         if (d->K[k] < 1) return fail(ESDG_EINVAL, "K[%d]=%d < 1", k, d->K[k]);
         if (!(d->hi[k] > d->lo[k])) return fail(ESDG_EINVAL, "hi[%d] <= lo[%d]", k, k);
@@ -743,8 +772,9 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         if ((rc0 = check_ptr(d->ref_rho, "ref_rho")) || (rc0 = check_ptr(d->ref_p, "ref_p")))
             return rc0;
     }
-    const int epw = d->epw ? d->epw : default_epw(d->N, d->precision);
-    if (d->curved ? !find_curved_variant(d->N, epw) : !has_variant(d->precision, d->N, epw))
+    const int epw = high ? 0 : (d->epw ? d->epw : default_epw(d->N, d->precision));
+    if (!high &&
+        (d->curved ? !find_curved_variant(d->N, epw) : !has_variant(d->precision, d->N, epw)))
         return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", d->N, epw);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -777,6 +807,15 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         return fail(ESDG_ENOMEM, "device allocation of the mesh tables failed");
     }
     m->footprint = (int64_t)(sizeof(double) * 4 * m->red_blocks) + 64;
+    if (high) {
+        const size_t pb = sizeof(double) * PRIM_VARS * (size_t)m->nn;
+        if (hipMalloc(&m->d_prim, pb) != hipSuccess) {
+            m->d_prim = nullptr;
+            esdg_mesh_destroy(m);
+            return fail(ESDG_ENOMEM, "device allocation of %.1f MB failed", pb / 1e6);
+        }
+        m->footprint += (int64_t)pb;
+    }
     hipError_t e8 = hipMemsetAsync(m->d_flag, 0, sizeof(int), m->stream);
     if (e8 != hipSuccess) {
         esdg_mesh_destroy(m);
@@ -813,6 +852,7 @@ int esdg_mesh_destroy(esdg_mesh_t m)
     }
     drop_graph(m);
     if (m->d_q2) (void)hipFree(m->d_q2);
+    if (m->d_prim) (void)hipFree(m->d_prim);
     if (m->d_r) (void)hipFree(m->d_r);
     if (m->d_partials) (void)hipFree(m->d_partials);
     if (m->d_red_out) (void)hipFree(m->d_red_out);
@@ -852,6 +892,12 @@ int esdg_set_epw(esdg_mesh_t m, int32_t epw)
 {
     int rc = check_mesh(m);
     if (rc) return rc;
+    if (m->N > N_FUSED_MAX) {
+        if (epw != 0)
+            return fail(ESDG_EINVAL, "orders above %d have no elements-per-workgroup variants",
+                        N_FUSED_MAX);
+        return ESDG_OK;
+    }
     const int e = epw ? epw : default_epw(m->N, m->desc.precision);
     if (m->curved ? !find_curved_variant(m->N, e) : !has_variant(m->desc.precision, m->N, e))
         return fail(ESDG_EINVAL, "no kernel variant for N=%d epw=%d", m->N, e);
@@ -1127,8 +1173,9 @@ extern "C" {
 
 int esdg_epw_options(int32_t N, int32_t precision, int32_t *out, int32_t cap)
 {
-    if (N < 1 || N > NQ_MAX - 1) return fail(ESDG_EINVAL, "N=%d outside 1..8", N);
+    if (N < 1 || N > NQ_MAX - 1) return fail(ESDG_EINVAL, "N=%d outside 1..%d", N, NQ_MAX - 1);
     int cnt = 0;
+    if (N > N_FUSED_MAX) return 0;  // the node-per-thread kernels of higher orders
     if (precision == ESDG_FP32_MIXED) {
         for (const MixedVariant &v : kMixedVariants)
             if (v.N == N) {
@@ -1191,6 +1238,8 @@ int esdg_pack_set_members(esdg_pack_t p, int32_t n, const esdg_mesh_t *meshes, d
     const esdg_mesh *m0 = meshes[0];
     if (!m0) return fail(ESDG_EINVAL, "NULL mesh");
     const int N = m0->N, prec = m0->desc.precision, epw = m0->epw;
+    if (N > N_FUSED_MAX)
+        return fail(ESDG_EINVAL, "packed stepping supports orders up to %d", N_FUSED_MAX);
     int64_t blocks = 0;
     const bool mixed = prec == ESDG_FP32_MIXED;
     std::string tab(mixed ? sizeof(PackMemberMixed) * n : sizeof(PackMember) * n, '\0');

@@ -33,7 +33,11 @@
 
 namespace esdg {
 
-constexpr int NQ_MAX = 9;  // polynomial order N <= 8
+// Polynomial orders N <= 15.  The fused line-per-lane kernels are compiled up
+// to N = 8 (N_FUSED_MAX); higher orders run the node-per-thread kernels of
+// esdg_high.hpp.
+constexpr int NQ_MAX = 16;
+constexpr int N_FUSED_MAX = 8;
 
 // Interface dissipation (values of esdg_mesh_desc.surface_flux).
 constexpr int SURF_RUSANOV = 0, SURF_EC = 1, SURF_MATRIX = 2;

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     assert set(esdg.SIGNATURES) == set(_declared())
 
 
-@pytest.mark.parametrize("N", range(1, 9))
+@pytest.mark.parametrize("N", range(1, 16))
 def test_library_lgl_tables_match_oracle(N):
     from paper_2605_16684_amd import esdg
     x, w, D = esdg.lgl_tables(N)
@@ -95,3 +95,26 @@ def test_invalid_arguments_fail_without_touching_the_device():
     assert "warp" in esdg.last_error()
     assert esdg.lib.esdg_rhs(None, None, None, 0.0) == esdg.ESDG_EINVAL
     assert esdg.lib.esdg_lgl_tables(9, None, None, None) == esdg.ESDG_EINVAL
+
+
+def test_high_orders_are_fp64_affine_and_unpacked():
+    from paper_2605_16684_amd import esdg
+    assert esdg.epw_options(12) == []
+    d = esdg.MeshDesc()
+    d.N = 16
+    d.K[:] = [1, 1, 1]
+    d.hi[:] = [1.0, 1.0, 1.0]
+    d.gamma, d.gas_R = 1.4, 287.0
+    h = C.c_void_p()
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    assert "N=16" in esdg.last_error()
+    d.N = 11
+    d.precision = esdg.FP32_MIXED
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    assert "FP64" in esdg.last_error()
+    d.precision = esdg.FP64
+    d.curved = 1
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
+    d.curved = 0
+    d.epw = 2
+    assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
