@@ -201,7 +201,8 @@ struct esdg_mesh {
     int epw;
     double h[3];
     double *d_q2;        // ping-pong state
-    double *d_prim;      // N > 8: per-node primitives [e][7][n] of the stage input
+    double *d_prim;      // N > 8 without the LDS kernel: per-node partner quantities [e][9][n]
+    bool high_lds;       // N > 8: one workgroup per element, primitives in LDS
     double *d_r;         // RHS scratch (entropy production)
     double *d_partials;  // reduction partials
     double *d_red_out;   // 4 doubles
@@ -432,10 +433,58 @@ int launch_stage_curved(esdg_mesh *m, StageParams P)
     return ESDG_OK;
 }
 
-// Orders above N_FUSED_MAX: primitives of the stage input, then the
-// node-per-thread stage (or RHS) kernel.
+// Workgroup size of stage_high_lds for order N.
+constexpr int high_lds_threads(int N)
+{
+    return N <= 9 ? 256 : 512;
+}
+
+template <int MODE, int T>
+void *high_lds_fn()
+{
+    return reinterpret_cast<void *>(&stage_high_lds<MODE, T>);
+}
+
+// Whether stage_high_lds can hold an element of order N on device dev: the
+// element's primitives must fit the workgroup's LDS, and the kernels accept
+// that much dynamic LDS.
+bool high_lds_fits(int dev, int N)
+{
+    int lim = 0;
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return false;
+    const size_t need = high_lds_bytes(N);
+    if (need > (size_t)lim) return false;
+    void *fns[] = {high_lds_fn<MODE_RHS, 256>(), high_lds_fn<MODE_STAGE, 256>(),
+                   high_lds_fn<MODE_RHS, 512>(), high_lds_fn<MODE_STAGE, 512>()};
+    for (void *f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+    return true;
+}
+
+// Orders above N_FUSED_MAX: one workgroup per element with the primitives in
+// LDS, or, where an element does not fit, the primitives of the stage input
+// into the prim buffer and then the node-per-thread kernel.
 int launch_stage_high(esdg_mesh *m, StageParams P)
 {
+    if (m->high_lds) {
+        if (m->ne > 0x7fffffff) return fail(ESDG_EINVAL, "mesh too large");
+        P.nblocks = (int)m->ne;
+        const size_t lds = high_lds_bytes(m->N);
+        const int T = high_lds_threads(m->N);
+        void (*k)(StageParams, int);
+        if (T == 256) k = P.mode == MODE_RHS ? stage_high_lds<MODE_RHS, 256>
+                                             : stage_high_lds<MODE_STAGE, 256>;
+        else k = P.mode == MODE_RHS ? stage_high_lds<MODE_RHS, 512>
+                                    : stage_high_lds<MODE_STAGE, 512>;
+        hipLaunchKernelGGL(k, dim3((unsigned)m->ne), dim3(T), lds, m->stream, P, m->N);
+        HIP_TRY(hipGetLastError());
+        return ESDG_OK;
+    }
     const int64_t nb = (m->nn + HIGH_THREADS - 1) / HIGH_THREADS;
     if (nb > 0x7fffffff) return fail(ESDG_EINVAL, "mesh too large");
     hipLaunchKernelGGL(prim_kernel, dim3((unsigned)nb), dim3(HIGH_THREADS), 0, m->stream, P, m->N,
@@ -807,7 +856,8 @@ int esdg_mesh_create(const esdg_mesh_desc *d, void *hip_stream, esdg_mesh_t *out
         return fail(ESDG_ENOMEM, "device allocation of the mesh tables failed");
     }
     m->footprint = (int64_t)(sizeof(double) * 4 * m->red_blocks) + 64;
-    if (high) {
+    m->high_lds = high && high_lds_fits(dev, m->N);
+    if (high && !m->high_lds) {
         const size_t pb = sizeof(double) * PRIM_VARS * (size_t)m->nn;
         if (hipMalloc(&m->d_prim, pb) != hipSuccess) {
             m->d_prim = nullptr;

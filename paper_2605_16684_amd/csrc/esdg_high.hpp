@@ -2,21 +2,25 @@
 //
 // The line-per-lane kernel of esdg_device.hpp holds a whole LGL line (its
 // primitives and sums) in one lane's registers; from N = 9 on that no longer
-// fits.  These orders take a node-per-thread path instead, in two launches
-// per stage (or RHS):
-//   1. prim_kernel: every node's primitives (rho, u/2, p/2, rho/p, p/rho,
-//      the quantities of the two-point flux, Sec. 4.1) into a per-mesh
-//      buffer prim[e][7][n] (56 B per node);
-//   2. stage_high_kernel: one thread per node evaluates the same semi-discrete
-//      right-hand side as the fused kernel -- for each direction r the full
-//      sweep over the node's r-line partners b != a, T_ab (S_ab + G_ab) with
-//      the entropy-conservative flux and the gravity term, the face flux and
-//      lift where the node lies on a face, the Coriolis source -- and writes
-//      R or applies the LSRK(5,4) stage update.
-// The partners' primitives come from the prim buffer (L2); each ordered
-// pair is evaluated by both of its nodes (no flux-symmetry saving: a thread
-// owns one node's sum).  Log-means take the branch rule of the fused kernel
-// with logarithms only on the log branch.
+// fits.  These orders take a node-per-thread path instead: one thread per
+// node evaluates the same semi-discrete right-hand side as the fused kernel
+// -- for each direction r the full sweep over the node's r-line partners
+// b != a, T_ab (S_ab + G_ab) with the entropy-conservative flux and the
+// gravity term, the face flux and lift where the node lies on a face, the
+// Coriolis source -- and writes R or applies the LSRK(5,4) stage update.
+// Each ordered pair is evaluated by both of its nodes (no flux-symmetry
+// saving: a thread owns one node's sum).  Log-means take the branch rule of
+// the fused kernel with logarithms only on the log branch.
+//
+// The partners' primitives (rho, u/2, p/2, rho/p: the quantities of the
+// two-point flux, Sec. 4.1) are formed once per node and per stage:
+//   - stage_high_lds: one workgroup per element; the element's partner
+//     quantities (with the per-node logarithms, 64 B per node) go to LDS,
+//     then every thread sweeps its nodes' lines out of LDS.  Used where the
+//     element fits the workgroup's LDS (N <= 12 on gfx950's 160 KB).
+//   - prim_kernel + stage_high_kernel: otherwise, a per-mesh buffer
+//     prim[e][9][n] (72 B per node) written by a first launch and read by the
+//     node-per-thread launch through L2.
 #pragma once
 
 #include "esdg_device.hpp"
@@ -24,7 +28,11 @@
 namespace esdg {
 
 constexpr int HIGH_THREADS = 256;
-constexpr int PRIM_VARS = 7;  // r, h0, h1, h2, hp, z, zi
+// Per-node quantities of the partners: r, h0, h1, h2, hp, z and the
+// logarithms ln(r), ln(z z_s^-1) of the log branch (the paper's per-node logs,
+// Sec. 4.1), laid out [var][n] per element.  The prim buffer adds p/rho.
+constexpr int PARTNER_VARS = 8;
+constexpr int PRIM_VARS = 9;
 
 __device__ __forceinline__ double phi_node(const StageParams &P, const OrderTables &tb, int ez,
                                            int k)
@@ -36,7 +44,21 @@ __device__ __forceinline__ double phi_node(const StageParams &P, const OrderTabl
     return P.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
 }
 
-// Primitives of every node of q_in.
+// The partner quantities of one node into an element block [var][NP].
+__device__ __forceinline__ void store_partner(double *__restrict__ pb, int NP, const Node &nd,
+                                              double lnz_scale)
+{
+    pb[0] = nd.r;
+    pb[NP] = nd.h0;
+    pb[2 * NP] = nd.h1;
+    pb[3 * NP] = nd.h2;
+    pb[4 * NP] = nd.hp;
+    pb[5 * NP] = nd.z;
+    pb[6 * NP] = log(nd.r);
+    pb[7 * NP] = log(nd.z * lnz_scale);
+}
+
+// Primitives and logarithms of every node of q_in.
 __global__ void __launch_bounds__(HIGH_THREADS)
     prim_kernel(const StageParams P, int N, double *__restrict__ prim)
 {
@@ -51,13 +73,8 @@ __global__ void __launch_bounds__(HIGH_THREADS)
     load_cons(P.q_in, e, NP, n, c);
     const Node nd = primitives(c, phi_node(P, tb, ez, n / (NQ * NQ)), P.gamma - 1.0);
     double *o = prim + e * PRIM_VARS * NP + n;
-    o[0] = nd.r;
-    o[NP] = nd.h0;
-    o[2 * NP] = nd.h1;
-    o[3 * NP] = nd.h2;
-    o[4 * NP] = nd.hp;
-    o[5 * NP] = nd.z;
-    o[6 * NP] = nd.zi;
+    store_partner(o, NP, nd, P.lnz_scale);
+    o[8 * NP] = nd.zi;
 }
 
 __device__ __forceinline__ Node load_prim(const double *__restrict__ prim, int64_t e, int NP,
@@ -71,36 +88,24 @@ __device__ __forceinline__ Node load_prim(const double *__restrict__ prim, int64
     nd.h2 = p[3 * NP];
     nd.hp = p[4 * NP];
     nd.z = p[5 * NP];
-    nd.zi = p[6 * NP];
+    nd.zi = p[8 * NP];
     return nd;
 }
 
-// {{x}}_log and 1/{{x}}_log of one pair with the branch rule of the fused
-// kernel, logarithms (of x scaled by `scale`) only on the log branch.
-__device__ __forceinline__ double log_mean_lazy(double xa, double xb)
+// Partner primitives from an element block laid out [var][NP] (global prim
+// buffer or LDS); the partner's p/rho is not needed, its logarithms are read
+// where a pair takes the log branch.
+__device__ __forceinline__ Node load_partner(const double *__restrict__ pb, int NP, int n)
 {
-    const double d = xb - xa, s = xa + xb;
-    const bool ser = fabs(d) < LM_SQRT_EPS * s;
-    double den = s;
-    if (!ser) den = log(xb) - log(xa);
-    const double x = fdiv(d, den);
-    const double u = x * x;
-    return ser ? 0.5 * s * (1.0 - u * (S1 + u * (S2 + u * S3))) : x;
-}
-
-__device__ __forceinline__ double inv_log_mean_lazy(double xa, double xb, double scale)
-{
-    const double d = xb - xa, s = xa + xb;
-    const bool ser = fabs(d) < LM_SQRT_EPS * s;
-    double num = 1.0, den = s;
-    if (!ser) {
-        num = log(xb * scale) - log(xa * scale);
-        den = d;
-    }
-    const double x = fdiv(num, den);
-    const double dx = d * x;
-    const double u = dx * dx;
-    return ser ? 2.0 * x * (1.0 + u * (I1 + u * (I2 + u * I3))) : x;
+    Node nd;
+    nd.r = pb[n];
+    nd.h0 = pb[NP + n];
+    nd.h1 = pb[2 * NP + n];
+    nd.h2 = pb[3 * NP + n];
+    nd.hp = pb[4 * NP + n];
+    nd.z = pb[5 * NP + n];
+    nd.zi = 0.0;
+    return nd;
 }
 
 // Node of the r-line through node (i, j, k) at position t.
@@ -116,10 +121,9 @@ __device__ __forceinline__ int line_pos_node(int NQ, int i, int j, int k, int t)
 // flux (unscaled: the caller multiplies by 2/h_R).
 template <int R>
 __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTables &tb, int N,
-                                           const double *__restrict__ prim, int64_t e,
-                                           const int ec[3], int i, int j, int k,
-                                           const Node &a, const Cons &qa, double phi_a,
-                                           double acc[5])
+                                           const double *__restrict__ pb, const int ec[3], int i,
+                                           int j, int k, const Node &a, const Cons &qa,
+                                           double phi_a, double acc[5])
 {
     const int NQ = N + 1, NP = NQ * NQ * NQ;
     const int ia = R == 0 ? i : (R == 1 ? j : k);
@@ -152,12 +156,15 @@ __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTabl
     }
     if (!(P.mask & TERM_VOL)) return;
     const int ez = ec[2];
+    const int na = line_pos_node<R>(NQ, i, j, k, ia);
+    const double lra = pb[6 * NP + na], lza = pb[7 * NP + na];
     for (int t = 0; t < NQ; ++t) {
         if (t == ia) continue;
-        const Node b = load_prim(prim, e, NP, line_pos_node<R>(NQ, i, j, k, t));
+        const int nb = line_pos_node<R>(NQ, i, j, k, t);
+        const Node b = load_partner(pb, NP, nb);
         const double phi_b = R == 2 ? phi_node(P, tb, ez, t) : phi_a;
-        const double rho_ln = log_mean_lazy(a.r, b.r);
-        const double izln = inv_log_mean_lazy(a.z, b.z, P.lnz_scale);
+        const double rho_ln = log_mean(a.r, b.r, lra, pb[6 * NP + nb]);
+        const double izln = inv_log_mean(a.z, b.z, lza, pb[7 * NP + nb]);
         const double hRa = hcomp<R>(a), hRb = hcomp<R>(b);
         const double frho = rho_ln * (hRa + hRb);
         double S[5];
@@ -180,35 +187,26 @@ __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTabl
     }
 }
 
+// R at node n = (i, j, k) of element e (partner primitives in pb), then the
+// RHS store or the LSRK stage update of that node, and the flag check.
 template <int MODE>
-__global__ void __launch_bounds__(HIGH_THREADS)
-    stage_high_kernel(const StageParams P, int N, const double *__restrict__ prim)
+__device__ __forceinline__ void high_node(const StageParams &P, const OrderTables &tb, int N,
+                                          const double *__restrict__ pb, int64_t e,
+                                          const int ec[3], int n, const Cons &qa, const Node &a)
 {
     const int NQ = N + 1, NQ2 = NQ * NQ, NP = NQ2 * NQ;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= P.ne * NP) return;
-    const int64_t e = gid / NP;
-    const int n = (int)(gid - e * NP);
     const int i = n % NQ, j = (n / NQ) % NQ, k = n / NQ2;
-    int ec[3];
-    ec[0] = (int)(e % P.K[0]);
-    ec[1] = (int)((e / P.K[0]) % P.K[1]);
-    ec[2] = (int)(e / ((int64_t)P.K[0] * P.K[1]));
-    const OrderTables &tb = c_tab[N - 1];
-    Cons qa;
-    load_cons(P.q_in, e, NP, n, qa);
-    const Node a = load_prim(prim, e, NP, n);
     const double phi_a = phi_node(P, tb, ec[2], k);
     double Rv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (P.mask & (TERM_VOL | TERM_FACE)) {
         double acc[5];
-        node_terms<0>(P, tb, N, prim, e, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<0>(P, tb, N, pb, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[0] * acc[v];
-        node_terms<1>(P, tb, N, prim, e, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<1>(P, tb, N, pb, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[1] * acc[v];
-        node_terms<2>(P, tb, N, prim, e, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<2>(P, tb, N, pb, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[2] * acc[v];
     }
@@ -234,6 +232,67 @@ __global__ void __launch_bounds__(HIGH_THREADS)
         const double kin = qa.v[1] * qa.v[1] + qa.v[2] * qa.v[2] + qa.v[3] * qa.v[3];
         const double eint = qa.v[4] - 0.5 * kin / r - r * phi_a;
         if (!(r > 0.0) || !(eint > 0.0)) atomicOr(P.flag, 1);
+    }
+}
+
+__device__ __forceinline__ void elem_coords(const StageParams &P, int64_t e, int ec[3])
+{
+    ec[0] = (int)(e % P.K[0]);
+    ec[1] = (int)((e / P.K[0]) % P.K[1]);
+    ec[2] = (int)(e / ((int64_t)P.K[0] * P.K[1]));
+}
+
+// Node-per-thread stage reading the partners from the prim buffer.
+template <int MODE>
+__global__ void __launch_bounds__(HIGH_THREADS)
+    stage_high_kernel(const StageParams P, int N, const double *__restrict__ prim)
+{
+    const int NQ = N + 1, NP = NQ * NQ * NQ;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= P.ne * NP) return;
+    const int64_t e = gid / NP;
+    const int n = (int)(gid - e * NP);
+    int ec[3];
+    elem_coords(P, e, ec);
+    const OrderTables &tb = c_tab[N - 1];
+    Cons qa;
+    load_cons(P.q_in, e, NP, n, qa);
+    const Node a = load_prim(prim, e, NP, n);
+    high_node<MODE>(P, tb, N, prim + e * PRIM_VARS * NP, e, ec, n, qa, a);
+}
+
+// Bytes of LDS stage_high_lds needs for one element of order N.
+inline size_t high_lds_bytes(int N)
+{
+    return sizeof(double) * PARTNER_VARS * (size_t)((N + 1) * (N + 1) * (N + 1));
+}
+
+// One workgroup per element (the grid has one block per element; blocks are
+// dealt to the XCDs so that each walks a contiguous range of elements).  The
+// element's primitives are formed once into LDS, then each thread finishes
+// its nodes n = tid, tid + THREADS, ...
+template <int MODE, int THREADS>
+__global__ void __launch_bounds__(THREADS) stage_high_lds(const StageParams P, int N)
+{
+    extern __shared__ double sprim[];  // [PARTNER_VARS][NP]
+    const int NQ = N + 1, NQ2 = NQ * NQ, NP = NQ2 * NQ;
+    const int64_t e = xcd_remap(blockIdx.x, P.nblocks);
+    int ec[3];
+    elem_coords(P, e, ec);
+    const OrderTables &tb = c_tab[N - 1];
+    const double gm1 = P.gamma - 1.0;
+    for (int n = threadIdx.x; n < NP; n += THREADS) {
+        Cons c;
+        load_cons(P.q_in, e, NP, n, c);
+        const Node nd = primitives(c, phi_node(P, tb, ec[2], n / NQ2), gm1);
+        store_partner(sprim + n, NP, nd, P.lnz_scale);
+    }
+    __syncthreads();
+    for (int n = threadIdx.x; n < NP; n += THREADS) {
+        Cons qa;
+        load_cons(P.q_in, e, NP, n, qa);
+        const Node a = primitives(qa, phi_node(P, tb, ec[2], n / NQ2), gm1);
+        high_node<MODE>(P, tb, N, sprim, e, ec, n, qa, a);
     }
 }
 
