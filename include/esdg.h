@@ -62,11 +62,13 @@ typedef struct esdg_mesh *esdg_mesh_t;
 /* Mesh description (paper Sec. 3 and the test-case geometry of Sec. 5).
  *   N            polynomial order, 1..15 (Nq = N+1 nodes per direction).
  *                Orders 1..8 run the fused line-per-lane stage kernels;
- *                orders 9..15 run a node-per-thread path (per-node
- *                primitives, then the stage or RHS kernel: two launches,
- *                56 B per node of device scratch held by the mesh), FP64
- *                on the affine box only, without elements-per-workgroup
- *                variants (epw must be 0) and not packable
+ *                orders 9..15 run a node-per-thread path, FP64 on the
+ *                affine box only, without elements-per-workgroup variants
+ *                (epw must be 0) and not packable: one workgroup per element
+ *                with the element's primitives in LDS where they fit the
+ *                device's LDS per workgroup (N <= 12 on gfx950), else two
+ *                launches per stage through a per-node buffer of 72 B held
+ *                by the mesh (counted in its footprint)
  *   K[3]         elements per direction
  *   lo/hi[3]     box corners in metres
  *   periodic[3]  1 = periodic in that direction, 0 = reflecting walls

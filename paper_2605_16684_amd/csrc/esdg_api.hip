@@ -433,16 +433,20 @@ int launch_stage_curved(esdg_mesh *m, StageParams P)
     return ESDG_OK;
 }
 
-// Workgroup size of stage_high_lds for order N.
+// Launch shape of stage_high_lds: waves per SIMD it is compiled for, and the
+// workgroup size below and from N = 10 on, where one element's LDS leaves
+// room for two workgroups per CU (N = 9) or one.
+constexpr int HIGH_LDS_WAVES = 1;
+constexpr int HIGH_LDS_T_SMALL = 256, HIGH_LDS_T_LARGE = 512;
 constexpr int high_lds_threads(int N)
 {
-    return N <= 9 ? 256 : 512;
+    return N <= 9 ? HIGH_LDS_T_SMALL : HIGH_LDS_T_LARGE;
 }
 
 template <int MODE, int T>
 void *high_lds_fn()
 {
-    return reinterpret_cast<void *>(&stage_high_lds<MODE, T>);
+    return reinterpret_cast<void *>(&stage_high_lds<MODE, T, HIGH_LDS_WAVES>);
 }
 
 // Whether stage_high_lds can hold an element of order N on device dev: the
@@ -455,8 +459,10 @@ bool high_lds_fits(int dev, int N)
         return false;
     const size_t need = high_lds_bytes(N);
     if (need > (size_t)lim) return false;
-    void *fns[] = {high_lds_fn<MODE_RHS, 256>(), high_lds_fn<MODE_STAGE, 256>(),
-                   high_lds_fn<MODE_RHS, 512>(), high_lds_fn<MODE_STAGE, 512>()};
+    void *fns[] = {high_lds_fn<MODE_RHS, HIGH_LDS_T_SMALL>(),
+                   high_lds_fn<MODE_STAGE, HIGH_LDS_T_SMALL>(),
+                   high_lds_fn<MODE_RHS, HIGH_LDS_T_LARGE>(),
+                   high_lds_fn<MODE_STAGE, HIGH_LDS_T_LARGE>()};
     for (void *f : fns)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) !=
             hipSuccess) {
@@ -476,11 +482,12 @@ int launch_stage_high(esdg_mesh *m, StageParams P)
         P.nblocks = (int)m->ne;
         const size_t lds = high_lds_bytes(m->N);
         const int T = high_lds_threads(m->N);
+        constexpr int TS = HIGH_LDS_T_SMALL, TL = HIGH_LDS_T_LARGE, W = HIGH_LDS_WAVES;
         void (*k)(StageParams, int);
-        if (T == 256) k = P.mode == MODE_RHS ? stage_high_lds<MODE_RHS, 256>
-                                             : stage_high_lds<MODE_STAGE, 256>;
-        else k = P.mode == MODE_RHS ? stage_high_lds<MODE_RHS, 512>
-                                    : stage_high_lds<MODE_STAGE, 512>;
+        if (T == TS) k = P.mode == MODE_RHS ? stage_high_lds<MODE_RHS, TS, W>
+                                            : stage_high_lds<MODE_STAGE, TS, W>;
+        else k = P.mode == MODE_RHS ? stage_high_lds<MODE_RHS, TL, W>
+                                    : stage_high_lds<MODE_STAGE, TL, W>;
         hipLaunchKernelGGL(k, dim3((unsigned)m->ne), dim3(T), lds, m->stream, P, m->N);
         HIP_TRY(hipGetLastError());
         return ESDG_OK;

@@ -271,8 +271,8 @@ inline size_t high_lds_bytes(int N)
 // dealt to the XCDs so that each walks a contiguous range of elements).  The
 // element's primitives are formed once into LDS, then each thread finishes
 // its nodes n = tid, tid + THREADS, ...
-template <int MODE, int THREADS>
-__global__ void __launch_bounds__(THREADS) stage_high_lds(const StageParams P, int N)
+template <int MODE, int THREADS, int WAVES>
+__global__ void __launch_bounds__(THREADS, WAVES) stage_high_lds(const StageParams P, int N)
 {
     extern __shared__ double sprim[];  // [PARTNER_VARS][NP]
     const int NQ = N + 1, NQ2 = NQ * NQ, NP = NQ2 * NQ;
