@@ -107,8 +107,9 @@ def cmd_traffic(a):
         if os.path.exists(a.json):
             with open(a.json) as f:
                 data = json.load(f)
-        ent = data.setdefault(a.workload, {})
         for name, r in rec.items():
+            # the curved kernels of a run are recorded under the warped mesh's workload
+            ent = data.setdefault(a.workload + ("_curved" if "stage_curved" in name else ""), {})
             key = "stage_fp64" if (r["mode"] == "stage" and "stage_fp64" in name) else name
             r = dict(r, kernel=name,
                      kernel_hash=perfmodel.kernel_source_hash(
