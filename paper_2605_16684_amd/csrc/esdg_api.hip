@@ -716,28 +716,43 @@ int setup_reference(esdg_mesh *m)
         hipMalloc(&m->d_rr_mom, sizeof(float) * 3 * nn) != hipSuccess)
         return fail(ESDG_ENOMEM, "reference buffers (%.1f MB)", 20.0 * nn / 1e6);
     m->footprint += (int64_t)(20 * nn);
-    int rc0;
-    if ((rc0 = ensure_scratch(m, &m->d_q2)) || (rc0 = ensure_scratch(m, &m->d_r))) return rc0;
+    // the FP64 reference state and its RHS are temporaries, allocated and
+    // freed in the stream's order: freeing them does not wait for what other
+    // streams have in flight on the device (hipFree would)
+    const size_t sb = sizeof(double) * (size_t)m->state_len;
+    double *tq = nullptr, *tr = nullptr;
+    if (hipMallocAsync((void **)&tq, sb, m->stream) != hipSuccess ||
+        hipMallocAsync((void **)&tr, sb, m->stream) != hipSuccess) {
+        if (tq) (void)hipFreeAsync(tq, m->stream);
+        (void)hipGetLastError();
+        return fail(ESDG_ENOMEM, "reference temporaries (%.1f MB)", 2.0 * sb / 1e6);
+    }
     GeomParams G = geom(m);
     const unsigned blocks = (unsigned)((nn + 255) / 256);
     hipLaunchKernelGGL(reference_state_kernel, dim3(blocks), dim3(256), 0, m->stream, G,
-                       m->desc.ref_rho, m->desc.ref_p, m->d_ref_r, m->d_ref_p, m->d_q2);
-    HIP_TRY(hipGetLastError());
-    StageParams P = base_params(m);
-    P.mode = MODE_RHS;
-    P.q_in = m->d_q2;
-    P.r_out = m->d_r;
-    P.flag = nullptr;
-    const int epw = find_variant(m->N, m->epw) ? m->epw : default_epw(m->N);
-    int rc = launch_stage_fp64(m, P, epw);
+                       m->desc.ref_rho, m->desc.ref_p, m->d_ref_r, m->d_ref_p, tq);
+    hipError_t el = hipGetLastError();
+    int rc = ESDG_OK;
+    if (el == hipSuccess) {
+        StageParams P = base_params(m);
+        P.mode = MODE_RHS;
+        P.q_in = tq;
+        P.r_out = tr;
+        P.flag = nullptr;
+        const int epw = find_variant(m->N, m->epw) ? m->epw : default_epw(m->N);
+        rc = launch_stage_fp64(m, P, epw);
+        if (!rc) {
+            hipLaunchKernelGGL(reference_rhs_kernel, dim3(blocks), dim3(256), 0, m->stream, m->ne,
+                               m->Np, (const double *)tr, m->d_rr_mom);
+            el = hipGetLastError();
+        }
+    }
+    (void)hipFreeAsync(tq, m->stream);
+    (void)hipFreeAsync(tr, m->stream);
     if (rc) return rc;
-    hipLaunchKernelGGL(reference_rhs_kernel, dim3(blocks), dim3(256), 0, m->stream, m->ne,
-                       m->Np, (const double *)m->d_r, m->d_rr_mom);
-    HIP_TRY(hipGetLastError());
+    if (el != hipSuccess) return fail(ESDG_EHIP, "%s", hipGetErrorString(el));
+    // the caller's reference arrays are read by then
     HIP_TRY(hipStreamSynchronize(m->stream));
-    // the temporaries are re-allocated on demand
-    release_scratch(m, &m->d_q2);
-    release_scratch(m, &m->d_r);
     return ESDG_OK;
 }
 
@@ -1173,8 +1188,21 @@ struct esdg_pack {
     int **d_flagptrs;    // each member mesh's non-physical flag
     int *d_flags;        // gathered flags
     int *h_flags;        // pinned copy of d_flags
+    char *h_stage;       // pinned staging of the uploads: table, parity, flag pointers
     hipGraphExec_t graph;
 };
+
+// Byte offsets of the parity and flag-pointer uploads in a staging buffer for
+// cap members, and its size.
+static inline size_t pack_stage_parity(int cap)
+{
+    return std::max(sizeof(PackMember), sizeof(PackMemberMixed)) * cap;
+}
+static inline size_t pack_stage_fptrs(int cap)
+{
+    return (pack_stage_parity(cap) + sizeof(int) * cap + 15) & ~(size_t)15;
+}
+static inline size_t pack_stage_bytes(int cap) { return pack_stage_fptrs(cap) + sizeof(int *) * cap; }
 
 namespace {
 
@@ -1281,6 +1309,7 @@ int esdg_pack_destroy(esdg_pack_t p)
     if (p->d_flagptrs) (void)hipFree(p->d_flagptrs);
     if (p->d_flags) (void)hipFree(p->d_flags);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
     delete p;
     return rc;
 }
@@ -1358,19 +1387,22 @@ int esdg_pack_set_members(esdg_pack_t p, int32_t n, const esdg_mesh_t *meshes, d
         void *members = nullptr;
         int *par = nullptr, *flags = nullptr, *hflags = nullptr;
         int **fptrs = nullptr;
+        char *stage = nullptr;
         const bool ok =
             hipMalloc(&members, std::max(sizeof(PackMember), sizeof(PackMemberMixed)) * cap) ==
                 hipSuccess &&
             hipMalloc(&par, sizeof(int) * cap) == hipSuccess &&
             hipMalloc(&fptrs, sizeof(int *) * cap) == hipSuccess &&
             hipMalloc(&flags, sizeof(int) * cap) == hipSuccess &&
-            hipHostMalloc(&hflags, sizeof(int) * cap, hipHostMallocDefault) == hipSuccess;
+            hipHostMalloc(&hflags, sizeof(int) * cap, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&stage, pack_stage_bytes(cap), hipHostMallocDefault) == hipSuccess;
         if (!ok) {
             if (members) (void)hipFree(members);
             if (par) (void)hipFree(par);
             if (fptrs) (void)hipFree(fptrs);
             if (flags) (void)hipFree(flags);
             if (hflags) (void)hipHostFree(hflags);
+            if (stage) (void)hipHostFree(stage);
             return fail(ESDG_ENOMEM, "pack table allocation failed");
         }
         if (p->d_members) (void)hipFree(p->d_members);
@@ -1378,23 +1410,32 @@ int esdg_pack_set_members(esdg_pack_t p, int32_t n, const esdg_mesh_t *meshes, d
         if (p->d_flagptrs) (void)hipFree(p->d_flagptrs);
         if (p->d_flags) (void)hipFree(p->d_flags);
         if (p->h_flags) (void)hipHostFree(p->h_flags);
+        if (p->h_stage) (void)hipHostFree(p->h_stage);
         p->d_members = members;
         p->d_parity = par;
         p->d_flagptrs = fptrs;
         p->d_flags = flags;
         p->h_flags = hflags;
+        p->h_stage = stage;
         p->capacity = cap;
     }
     // from here on the device table no longer matches the old member set:
     // a failed upload leaves an empty pack, whose step() is rejected
     p->n = 0;
-    HIP_TRY(hipMemcpyAsync(p->d_members, tab.data(), tab.size(), hipMemcpyHostToDevice,
+    // uploads from the pinned staging buffer, ordered on the pack's stream
+    // before the next step; the stream was idle when the buffer was filled,
+    // and the next call waits for it before refilling
+    char *st_par = p->h_stage + pack_stage_parity(p->capacity);
+    char *st_fp = p->h_stage + pack_stage_fptrs(p->capacity);
+    std::memcpy(p->h_stage, tab.data(), tab.size());
+    std::memcpy(st_par, parity, sizeof(int32_t) * n);
+    std::memcpy(st_fp, flagptrs.data(), sizeof(int *) * n);
+    HIP_TRY(hipMemcpyAsync(p->d_members, p->h_stage, tab.size(), hipMemcpyHostToDevice,
                            p->stream));
-    HIP_TRY(hipMemcpyAsync(p->d_parity, parity, sizeof(int32_t) * n, hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(p->d_parity, st_par, sizeof(int32_t) * n, hipMemcpyHostToDevice,
                            p->stream));
-    HIP_TRY(hipMemcpyAsync(p->d_flagptrs, flagptrs.data(), sizeof(int *) * n,
-                           hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_flagptrs, st_fp, sizeof(int *) * n, hipMemcpyHostToDevice,
+                           p->stream));
     p->n = n;
     p->N = N;
     p->precision = prec;

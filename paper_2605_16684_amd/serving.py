@@ -6,7 +6,9 @@ server
 
 * admits arrived requests while their device footprint fits the HBM budget
   (FIFO with backfill: a request that does not fit does not block smaller
-  ones behind it), keeping every member's state resident on the device;
+  ones behind it), keeping every member's state resident on the device; a
+  member's mesh, initial state and time step are prepared off the
+  scheduler's thread, which meanwhile keeps launching the buckets' steps;
 * groups members by (N, precision) into buckets; each bucket is one packed
   launch per stage over all its members (``esdg.Pack``: a device descriptor
   table, one step = 5 packed stage kernels + a parity flip captured in a
@@ -29,10 +31,12 @@ on a machine without a GPU.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import json
 import math
 import os
+import threading
 import time
 from typing import Dict, List, Optional, Tuple
 
@@ -169,16 +173,22 @@ class Autotuner:
         return {"epw": int(best), "ms": timings, "nodes": req.nodes}
 
 
-def _make_member_mesh(req: Request, epw: int = 0):
+def _make_member_mesh(req: Request, epw: int = 0, retire=None):
     """Library mesh, initial state (built in device memory) and the FP32-mixed
-    reference arrays of a request."""
+    reference arrays of a request.  The FP64 mesh that supplies the node
+    coordinates of an FP32-mixed request is destroyed here, or handed to
+    `retire(mesh)` to be destroyed later (destroying a mesh waits for the
+    device)."""
     import torch
     from . import esdg
     spec = req.spec()
     if req.precision == FP32_MIXED:
         probe = esdg.Mesh(spec, epw=0)
         xyz = probe.coords()
-        probe.close()
+        if retire is None:
+            probe.close()
+        else:
+            retire(probe)
         rr, pr = W.reference_state(xyz, spec, req.kind)
         m = esdg.Mesh(spec, precision=esdg.FP32_MIXED, ref_rho=rr.contiguous(),
                       ref_p=pr.contiguous(), epw=epw)
@@ -231,6 +241,17 @@ class GpuExecutor:
         # no step is in flight
         self._retired: List[object] = []
         self._retired_bytes = 0
+        self._lock = threading.Lock()
+        # admissions run on one worker thread: building a member's mesh and
+        # state and reading its time step wait for the device, and the
+        # scheduler's thread keeps launching steps meanwhile
+        self.device = torch.cuda.current_device()
+        self._pool = concurrent.futures.ThreadPoolExecutor(
+            max_workers=1, thread_name_prefix="esdg-admission")
+        # the admission thread's work goes to a stream of its own (not the
+        # null stream, whose implicit ordering with other streams would
+        # invalidate a graph capture running on the scheduler's thread)
+        self._admit_stream = torch.cuda.Stream()
 
     def now(self) -> float:
         return time.perf_counter() - self.t0_host
@@ -238,11 +259,26 @@ class GpuExecutor:
     def _dev_time(self, ev) -> float:
         return self.ev0.elapsed_time(ev) * 1e-3
 
+    def admit_async(self, req: Request) -> concurrent.futures.Future:
+        """Prepare a member on the admission thread; the future's result is
+        what `admit` returns."""
+        return self._pool.submit(self.admit, req)
+
     def admit(self, req: Request):
+        """Mesh, initial state, ping-pong and dq buffers and time step of a
+        new member, complete on the device when this returns."""
         torch = self.torch
         t0 = time.perf_counter()
+        torch.cuda.set_device(self.device)
+        with torch.cuda.stream(self._admit_stream):
+            out = self._admit(req)
+        self.times["admission_s"] += time.perf_counter() - t0
+        return out
+
+    def _admit(self, req: Request):
+        torch = self.torch
         epw = self.autotuner.epw(req.N, req.precision)
-        m, q, xyz = _make_member_mesh(req, epw=epw)
+        m, q, xyz = _make_member_mesh(req, epw=epw, retire=self._retire_mesh)
         del xyz
         try:
             dt = m.cfl_dt(q, 0.5)
@@ -255,8 +291,8 @@ class GpuExecutor:
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         ev.synchronize()
-        self.times["admission_s"] += time.perf_counter() - t0
-        return {"mesh": m, "bufs": [q, q1], "dq": dq, "dt": dt, "parity": 0}, self._dev_time(ev)
+        return ({"mesh": m, "bufs": [q, q1], "dq": dq, "dt": dt, "parity": 0, "ready": ev},
+                self._dev_time(ev))
 
     def set_bucket(self, key, members: List[Member]):
         from . import esdg
@@ -270,10 +306,14 @@ class GpuExecutor:
         with torch.cuda.stream(b["stream"]):
             if b["pack"] is None:
                 b["pack"] = esdg.Pack(b["stream"])
-            # states written on the default stream (initial states) must be
-            # visible to the bucket stream
-            b["stream"].wait_stream(torch.cuda.default_stream())
+            # initial states are written on the admission thread's stream:
+            # the bucket stream waits for each member's admission event (a
+            # no-op once it has completed, as it has when admit returned)
             hs = [mb.handle for mb in members]
+            for h in hs:
+                if h.get("ready") is not None:
+                    b["stream"].wait_event(h["ready"])
+                    h["ready"] = None
             b["pack"].set_members([h["mesh"] for h in hs], [h["bufs"][0] for h in hs],
                                   [h["bufs"][1] for h in hs], [h["dq"] for h in hs],
                                   [h["dt"] for h in hs], [h["parity"] for h in hs])
@@ -339,25 +379,30 @@ class GpuExecutor:
         result = None
         if self.keep_results and keep:
             result = h["bufs"][h["parity"]].cpu().numpy()
-        self._retired.append(h["mesh"])
-        self._retired_bytes += h["mesh"].footprint
+        self._retire_mesh(h["mesh"])
         mb.handle = None
         self.times["release_s"] += time.perf_counter() - t0
         return result
 
+    def _retire_mesh(self, m):
+        with self._lock:
+            self._retired.append(m)
+            self._retired_bytes += m.footprint
+
     def retired_bytes(self) -> int:
-        """Device bytes still held by the meshes of released members."""
+        """Device bytes still held by the meshes of released members (and by
+        the coordinate meshes of admitted FP32-mixed members)."""
         return self._retired_bytes
 
     def flush_retired(self):
         """Destroy the meshes of released members."""
-        if not self._retired:
+        with self._lock:
+            ms, self._retired, self._retired_bytes = self._retired, [], 0
+        if not ms:
             return
         t0 = time.perf_counter()
-        for m in self._retired:
+        for m in ms:
             m.close()
-        self._retired = []
-        self._retired_bytes = 0
         self.times["release_s"] += time.perf_counter() - t0
 
 
@@ -418,6 +463,15 @@ class FakeExecutor:
         self.live_bytes += footprint_bytes(req)
         self.peak_bytes = max(self.peak_bytes, self.live_bytes + self.retired)
         return {"parity": 0}, self.clock
+
+    def admit_async(self, req: Request) -> concurrent.futures.Future:
+        """Admission completes at once (its cost advances the virtual clock)."""
+        fut = concurrent.futures.Future()
+        try:
+            fut.set_result(self.admit(req))
+        except Exception as ex:  # noqa: BLE001 -- handed to the scheduler
+            fut.set_exception(ex)
+        return fut
 
     def set_bucket(self, key, members):
         self.buckets[key] = list(members)
@@ -580,8 +634,9 @@ class Server:
         flush = getattr(ex, "flush_retired", lambda: None)
         inflight: Dict[tuple, object] = {}      # bucket -> completion token of its step
         stepping: Dict[tuple, List[Member]] = {}  # bucket -> members of that step
+        admitting: List[tuple] = []             # (future, request, footprint)
         t_start = ex.now()
-        while pending or queue or any(active.values()) or inflight:
+        while pending or queue or admitting or any(active.values()) or inflight:
             now = ex.now() - t_start
             while pending and pending[0].arrival <= now:
                 r = pending.pop(0)
@@ -589,23 +644,31 @@ class Server:
                     rejected += 1
                     continue
                 queue.append(r)
-            # admission: FIFO with backfill
+            # admission: FIFO with backfill; the footprint is reserved at
+            # once, the member is prepared by the executor (asynchronously on
+            # the GPU) and joins its bucket when ready
             for r in list(queue):
                 fp = footprint_bytes(r)
                 if used + fp > self.budget:
                     continue
                 if used + retired() + fp > self.budget:
                     flush()
-                try:
-                    handle, t_adm = ex.admit(r)
-                except Exception:
-                    queue.remove(r)
-                    rejected += 1
-                    continue
                 queue.remove(r)
-                mb = Member(r, fp, handle, admitted=ex.now() - t_start, last_done=t_adm)
                 used += fp
                 peak = max(peak, used)
+                admitting.append((ex.admit_async(r), r, fp))
+            for item in list(admitting):
+                fut, r, fp = item
+                if not fut.done():
+                    continue
+                admitting.remove(item)
+                try:
+                    handle, t_adm = fut.result()
+                except Exception:
+                    used -= fp
+                    rejected += 1
+                    continue
+                mb = Member(r, fp, handle, admitted=ex.now() - t_start, last_done=t_adm)
                 active.setdefault(r.key, []).append(mb)
                 self.members[r.rid] = mb
                 dirty.add(r.key)
@@ -628,6 +691,11 @@ class Server:
                     stepping[key] = list(ms)  # members admitted later join after this step
                     steps_launched += 1
             if not inflight:
+                if admitting:
+                    # nothing to step until a member is ready
+                    concurrent.futures.wait([a[0] for a in admitting], timeout=0.05,
+                                            return_when=concurrent.futures.FIRST_COMPLETED)
+                    continue
                 flush()
                 if not pending and not queue:
                     break
@@ -642,6 +710,10 @@ class Server:
                             time.sleep(min(wait, 0.05))
                 continue
             until = t_start + pending[0].arrival if pending else None
+            if admitting:
+                # look again soon for members that have become ready
+                soon = ex.now() + 1e-3
+                until = soon if until is None else min(until, soon)
             for key, t_end in ex.poll(inflight, until).items():
                 del inflight[key]
                 # failure isolation: a member whose own flag reports a
