@@ -90,7 +90,7 @@ __device__ __forceinline__ void pair_log_means_series(const Node &a, const Node 
                                                       double &rho_ln, double &izln)
 {
     const double dr = b.r - a.r, sr = a.r + b.r;
-    const double xr = dr * frcp(sr);
+    const double xr = dr * frcp1(sr);  // enters only through u < 1e-4
     const double ur = xr * xr;
     rho_ln = sr * (0.5 - ur * (H1 + ur * (H2 + ur * H3)));
     const double dz = b.z - a.z, sz = a.z + b.z;

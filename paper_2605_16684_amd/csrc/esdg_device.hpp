@@ -155,13 +155,23 @@ __device__ __forceinline__ double frcp(double b)
     return fma(r, e, r);
 }
 
-// a/b: the refined reciprocal and one residual correction of the quotient
-// (Markstein's scheme).  For the normal, finite operands met here it agrees
-// with the IEEE quotient; it skips the range scaling and special-value
-// fix-up of the full division sequence.
+// 1/b by one Newton-Raphson step on the hardware reciprocal estimate (whose
+// relative error is below 2^-24 on gfx950): relative error below 3e-15, for
+// a reciprocal that only scales a small correction term, or that the
+// quotient's residual correction refines.
+__device__ __forceinline__ double frcp1(double b)
+{
+    const double r = __builtin_amdgcn_rcp(b);
+    return fma(r, fma(-b, r, 1.0), r);
+}
+
+// a/b: a once-refined reciprocal and one residual correction of the
+// quotient (Markstein's scheme), which leaves the quotient within about one
+// ulp of the IEEE one for the normal, finite operands met here; it skips the
+// range scaling and special-value fix-up of the full division sequence.
 __device__ __forceinline__ double fdiv(double a, double b)
 {
-    const double r = frcp(b);
+    const double r = frcp1(b);
     const double q = a * r;
     return fma(fma(-b, q, a), r, q);
 }
@@ -234,7 +244,7 @@ __device__ __forceinline__ double sym_flux_series(const Node &a, const Node &b, 
                                                   double gm1i, double S[5])
 {
     const double dr = b.r - a.r, sr = a.r + b.r;
-    const double xr = dr * frcp(sr);
+    const double xr = dr * frcp1(sr);  // enters only through u < 1e-4
     const double ur = xr * xr;
     const double rho_ln = sr * (0.5 - ur * (H1 + ur * (H2 + ur * H3)));
     const double dz = b.z - a.z, sz = a.z + b.z;

@@ -39,9 +39,10 @@ def test_packed_steps_equal_single_mesh_steps():
 
 def test_alone_and_in_the_mix_give_identical_results(tmp_path):
     tuner = S.Autotuner(str(tmp_path / "epw.json"), target_nodes=1.5e5)
-    # a burst (all arrive within microseconds): the budget, not the timing of
-    # the host, decides which members overlap
-    reqs = S.request_stream(n=8, seed=7, mean_interarrival=1e-6, steps=4, kmin=2, kmax=5,
+    # a burst (all arrive within microseconds) under a budget of half the
+    # total footprint; enough steps that members prepared one after the other
+    # on the admission thread overlap on the device
+    reqs = S.request_stream(n=8, seed=7, mean_interarrival=1e-6, steps=40, kmin=2, kmax=5,
                             orders=(3, 4))
     budget = int(0.5 * sum(S.footprint_bytes(r) for r in reqs))
     budget = max(budget, max(S.footprint_bytes(r) for r in reqs))
@@ -76,7 +77,9 @@ def test_nonphysical_member_fails_alone_in_a_mix(tmp_path):
     node: that request fails with NonPhysicalState, every other request ends
     bitwise equal to its solo run."""
     tuner = S.Autotuner(str(tmp_path / "epw.json"), target_nodes=1.5e5)
-    reqs = S.request_stream(n=6, seed=11, mean_interarrival=1e-6, steps=4, kmin=2, kmax=4,
+    # enough steps that members prepared one after the other on the
+    # admission thread still overlap on the device
+    reqs = S.request_stream(n=6, seed=11, mean_interarrival=1e-6, steps=40, kmin=2, kmax=4,
                             orders=(3, 4))
     bad = reqs[2]
     reqs[2] = S.Request(bad.rid, bad.kind, bad.K, bad.N, bad.precision, bad.seed, bad.steps,
