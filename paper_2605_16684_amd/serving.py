@@ -222,7 +222,8 @@ class Member:
 class GpuExecutor:
     """Drives libesdg: one Pack and one stream per (N, precision) bucket."""
 
-    def __init__(self, autotuner: Optional[Autotuner] = None, keep_results: bool = False):
+    def __init__(self, autotuner: Optional[Autotuner] = None, keep_results: bool = False,
+                 admission_threads: int = 2):
         import torch
         self.torch = torch
         self.autotuner = autotuner or Autotuner()
@@ -242,16 +243,16 @@ class GpuExecutor:
         self._retired: List[object] = []
         self._retired_bytes = 0
         self._lock = threading.Lock()
-        # admissions run on one worker thread: building a member's mesh and
+        # admissions run on worker threads: building a member's mesh and
         # state and reading its time step wait for the device, and the
         # scheduler's thread keeps launching steps meanwhile
         self.device = torch.cuda.current_device()
         self._pool = concurrent.futures.ThreadPoolExecutor(
-            max_workers=1, thread_name_prefix="esdg-admission")
-        # the admission thread's work goes to a stream of its own (not the
+            max_workers=max(1, int(admission_threads)), thread_name_prefix="esdg-admission")
+        # each admission thread's work goes to a stream of its own (not the
         # null stream, whose implicit ordering with other streams would
         # invalidate a graph capture running on the scheduler's thread)
-        self._admit_stream = torch.cuda.Stream()
+        self._tls = threading.local()
 
     def now(self) -> float:
         return time.perf_counter() - self.t0_host
@@ -260,24 +261,33 @@ class GpuExecutor:
         return self.ev0.elapsed_time(ev) * 1e-3
 
     def admit_async(self, req: Request) -> concurrent.futures.Future:
-        """Prepare a member on the admission thread; the future's result is
-        what `admit` returns."""
-        return self._pool.submit(self.admit, req)
+        """Prepare a member on an admission thread; the future's result is
+        what `admit` returns.  The elements per workgroup are looked up (and,
+        the first time for an (N, precision), tuned) on the calling thread,
+        which also captures the packs' graphs: tuning synchronises the
+        device."""
+        epw = self.autotuner.epw(req.N, req.precision)
+        return self._pool.submit(self.admit, req, epw)
 
-    def admit(self, req: Request):
+    def admit(self, req: Request, epw: Optional[int] = None):
         """Mesh, initial state, ping-pong and dq buffers and time step of a
         new member, complete on the device when this returns."""
         torch = self.torch
         t0 = time.perf_counter()
+        if epw is None:
+            epw = self.autotuner.epw(req.N, req.precision)
         torch.cuda.set_device(self.device)
-        with torch.cuda.stream(self._admit_stream):
-            out = self._admit(req)
-        self.times["admission_s"] += time.perf_counter() - t0
+        stream = getattr(self._tls, "stream", None)
+        if stream is None:
+            stream = self._tls.stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            out = self._admit(req, epw)
+        with self._lock:
+            self.times["admission_s"] += time.perf_counter() - t0
         return out
 
-    def _admit(self, req: Request):
+    def _admit(self, req: Request, epw: int):
         torch = self.torch
-        epw = self.autotuner.epw(req.N, req.precision)
         m, q, xyz = _make_member_mesh(req, epw=epw, retire=self._retire_mesh)
         del xyz
         try:
