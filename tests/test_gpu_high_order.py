@@ -142,3 +142,46 @@ def test_high_order_nonphysical_state_is_reported():
     with pytest.raises(esdg.NonPhysicalState):
         m.check()
     m.check()  # flag cleared
+
+
+@pytest.mark.parametrize("N", [10, 14])
+def test_high_order_diagnostics_match_oracle(N):
+    """Entropy, mass and energy integrals, the entropy production and the CFL
+    step at orders whose node loops run to 11-15 nodes per direction."""
+    esdg = _esdg()
+    spec = W.MeshSpec(N, (2, 1, 2), *_BOX, (1, 0, 0), coriolis_f=1e-4, surface_flux=0)
+    om = _oracle_mesh(spec)
+    q = W.state_iso_pert(om.coords(), spec, seed=N)
+    m = esdg.Mesh(spec)
+    qg = torch.from_numpy(q).cuda()
+    eg, eo = m.entropy(qg), om.entropy(q)
+    print(f"[N{N} entropy] gpu={eg} oracle={eo}", flush=True)
+    for k in range(3):
+        assert abs(eg[k] - eo[k]) <= 1e-13 * abs(eo[k])
+    r, g = om.rhs(q, gross=True)
+    v = np.stack([O.entropy_vars(q[e, :, n], om.phi()[e, n]) for e in range(om.ne)
+                  for n in range(om.Np)]).reshape(om.ne, om.Np, 5).transpose(0, 2, 1)
+    scale = np.abs(v * g).sum() * (om.h[0] * om.h[1] * om.h[2] / 8.0)
+    assert abs(eg[3] - eo[3]) <= 1e-12 * scale
+    assert eg[3] < 0.0  # Rusanov faces dissipate entropy
+    dt = m.cfl_dt(qg, 0.25)
+    assert abs(dt - om.cfl_dt(q, 0.25)) <= 1e-14 * dt
+
+
+@pytest.mark.parametrize("N,K", [(12, (2, 1, 2)), (15, (1, 1, 2))])
+def test_high_order_noalloc_step_matches_lsrk_step(N, K):
+    """The allocation-free step on the LDS kernel (N = 12) and on the
+    prim-buffer kernel (N = 15) gives the ordinary step's bits."""
+    esdg = _esdg()
+    spec = W.MeshSpec(N, K, *_BOX, (1, 0, 0), coriolis_f=1e-4, surface_flux=2)
+    m = esdg.Mesh(spec)
+    q0 = W.make_state("iso_pert", m.coords(), spec, seed=2).contiguous()
+    dt = m.cfl_dt(q0, 0.25)
+    qa, dqa = q0.clone(), torch.zeros_like(q0)
+    qb, dqb = q0.clone(), torch.full_like(q0, float("nan"))
+    for _ in range(2):
+        m.lsrk_step(qa, dqa, dt)
+        m.lsrk_step_noalloc(qb, dqb, dt)
+    m.check()
+    assert not torch.equal(qa, q0)
+    assert torch.equal(qa, qb) and torch.equal(dqa, dqb)
