@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c1", help="c0 | c1 | c2 | c3")
+    ap.add_argument("--workload", default="c1", help="c0 | c1 | c2 | c3 | h12 | h15")
     ap.add_argument("--epw", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -504,7 +504,8 @@ def main():
     flops_launch = perfmodel.flops_per_node(N, stage=True) * nn
     achieved_gbs = bytes_launch / t_launch / 1e9
     achieved_tf = flops_launch / t_launch / 1e12
-    kname = f"stage_fp64<{N + 1},{mesh.epw}>"
+    kname = (f"stage_fp64<{N + 1},{mesh.epw}>" if N <= 8 else
+             f"node-per-thread stage launches (N={N})")
     traffic = traffic_record("stage_fp64", wl.name if args.surface == "rusanov"
                              else f"{wl.name}_{args.surface}")
 

@@ -97,11 +97,24 @@ def channel(N=4, K=(160, 24, 10)) -> Workload:
                     "channel", 100)
 
 
+def high_order_box(N, K) -> Workload:
+    """Perturbed isothermal box of 1 km elements, periodic x/y, walls z, for
+    the orders 9..15 (CFL 0.25: the step rule's 0.5 is unstable from about
+    N = 12 on)."""
+    return Workload(f"iso_pert_box_{K[0]}x{K[1]}x{K[2]}_N{N}",
+                    MeshSpec(N, tuple(K), (0.0, 0.0, 0.0),
+                             (1000.0 * K[0], 1000.0 * K[1], 1000.0 * K[2]), (1, 1, 0)),
+                    "iso_pert", 20, cfl=0.25)
+
+
 WORKLOADS = {
     "c0": iso_pert_cube(),
     "c1": rising_bubble(),
     "c2": channel(),
     "c3": channel(N=7),
+    # orders above the fused kernel's: LDS kernel (N = 12), prim buffer (N = 15)
+    "h12": high_order_box(12, (10, 8, 8)),
+    "h15": high_order_box(15, (8, 8, 8)),
 }
 
 
