@@ -42,7 +42,7 @@ def test_alone_and_in_the_mix_give_identical_results(tmp_path):
     # a burst (all arrive within microseconds) under a budget of half the
     # total footprint; enough steps that members prepared one after the other
     # on the admission thread overlap on the device
-    reqs = S.request_stream(n=8, seed=7, mean_interarrival=1e-6, steps=40, kmin=2, kmax=5,
+    reqs = S.request_stream(n=8, seed=7, mean_interarrival=1e-6, steps=100, kmin=2, kmax=5,
                             orders=(3, 4))
     budget = int(0.5 * sum(S.footprint_bytes(r) for r in reqs))
     budget = max(budget, max(S.footprint_bytes(r) for r in reqs))
@@ -79,7 +79,7 @@ def test_nonphysical_member_fails_alone_in_a_mix(tmp_path):
     tuner = S.Autotuner(str(tmp_path / "epw.json"), target_nodes=1.5e5)
     # enough steps that members prepared one after the other on the
     # admission thread still overlap on the device
-    reqs = S.request_stream(n=6, seed=11, mean_interarrival=1e-6, steps=40, kmin=2, kmax=4,
+    reqs = S.request_stream(n=6, seed=11, mean_interarrival=1e-6, steps=100, kmin=2, kmax=4,
                             orders=(3, 4))
     bad = reqs[2]
     reqs[2] = S.Request(bad.rid, bad.kind, bad.K, bad.N, bad.precision, bad.seed, bad.steps,
