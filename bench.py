@@ -241,6 +241,7 @@ def serving_block(torch, throughput, n=96, steps=50, budget_gb=24.0, load=1.2, s
         t_tune = time.perf_counter() - t0
         srv = S.Server(budget, executor=S.GpuExecutor(tuner))
         st = srv.run(reqs)
+        srv.ex.close()
         table = {k: v["epw"] for k, v in tuner.table.items()}
     out = st.as_dict()
     out.update({"requests": n, "steps_per_request": steps, "mean_interarrival_s": mean_gap,

@@ -38,6 +38,7 @@ import math
 import os
 import threading
 import time
+import weakref
 from typing import Dict, List, Optional, Tuple
 
 import numpy as np
@@ -249,6 +250,8 @@ class GpuExecutor:
         self.device = torch.cuda.current_device()
         self._pool = concurrent.futures.ThreadPoolExecutor(
             max_workers=max(1, int(admission_threads)), thread_name_prefix="esdg-admission")
+        # the admission threads end with the executor
+        self._pool_finalizer = weakref.finalize(self, self._pool.shutdown, wait=False)
         # each admission thread's work goes to a stream of its own (not the
         # null stream, whose implicit ordering with other streams would
         # invalidate a graph capture running on the scheduler's thread)
@@ -256,6 +259,13 @@ class GpuExecutor:
 
     def now(self) -> float:
         return time.perf_counter() - self.t0_host
+
+    def close(self):
+        """Wait for the admission threads, end them, and destroy the meshes of
+        released members."""
+        self._pool.shutdown(wait=True)
+        self._pool_finalizer.detach()
+        self.flush_retired()
 
     def _dev_time(self, ev) -> float:
         return self.ev0.elapsed_time(ev) * 1e-3
