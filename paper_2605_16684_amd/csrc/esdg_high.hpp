@@ -118,10 +118,13 @@ __device__ __forceinline__ int line_pos_node(int NQ, int i, int j, int k, int t)
 }
 
 // Sum over direction R of the node's volume pairs and, on a face, its face
-// flux (unscaled: the caller multiplies by 2/h_R).
+// flux (unscaled: the caller multiplies by 2/h_R).  lflag (or NULL) marks
+// the lines of the element that can reach the log branch of a log-mean;
+// where no line of the wave's nodes can, the pairs take the series-only flux.
 template <int R>
 __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTables &tb, int N,
-                                           const double *__restrict__ pb, const int ec[3], int i,
+                                           const double *__restrict__ pb,
+                                           const unsigned char *lflag, const int ec[3], int i,
                                            int j, int k, const Node &a, const Cons &qa,
                                            double phi_a, double acc[5])
 {
@@ -156,6 +159,28 @@ __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTabl
     }
     if (!(P.mask & TERM_VOL)) return;
     const int ez = ec[2];
+    if (lflag) {
+        const int line = R == 0 ? j + NQ * k : (R == 1 ? i + NQ * k : i + NQ * j);
+        if (__ballot(lflag[R * NQ * NQ + line] != 0) == 0) {
+            // every pair of these lines takes the series branch of both log-means
+            for (int t = 0; t < NQ; ++t) {
+                if (t == ia) continue;
+                const Node b = load_partner(pb, NP, line_pos_node<R>(NQ, i, j, k, t));
+                const double phi_b = R == 2 ? phi_node(P, tb, ez, t) : phi_a;
+                double S[5];
+                const double rho_ln =
+                    sym_flux_series<R>(a, b, 0.5 * (phi_a + phi_b), gm1i, S);
+                const double tab = tb.T[ia][t];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] -= tab * S[v];
+                if (R == 2) {
+                    const double X = 0.25 * rho_ln * (a.z + b.z) * (phi_b - phi_a);
+                    acc[3] -= tab * (X * a.zi);
+                }
+            }
+            return;
+        }
+    }
     const int na = line_pos_node<R>(NQ, i, j, k, ia);
     const double lra = pb[6 * NP + na], lza = pb[7 * NP + na];
     for (int t = 0; t < NQ; ++t) {
@@ -191,7 +216,8 @@ __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTabl
 // RHS store or the LSRK stage update of that node, and the flag check.
 template <int MODE>
 __device__ __forceinline__ void high_node(const StageParams &P, const OrderTables &tb, int N,
-                                          const double *__restrict__ pb, int64_t e,
+                                          const double *__restrict__ pb,
+                                          const unsigned char *lflag, int64_t e,
                                           const int ec[3], int n, const Cons &qa, const Node &a)
 {
     const int NQ = N + 1, NQ2 = NQ * NQ, NP = NQ2 * NQ;
@@ -200,13 +226,13 @@ __device__ __forceinline__ void high_node(const StageParams &P, const OrderTable
     double Rv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (P.mask & (TERM_VOL | TERM_FACE)) {
         double acc[5];
-        node_terms<0>(P, tb, N, pb, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<0>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[0] * acc[v];
-        node_terms<1>(P, tb, N, pb, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<1>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[1] * acc[v];
-        node_terms<2>(P, tb, N, pb, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<2>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[2] * acc[v];
     }
@@ -258,13 +284,15 @@ __global__ void __launch_bounds__(HIGH_THREADS)
     Cons qa;
     load_cons(P.q_in, e, NP, n, qa);
     const Node a = load_prim(prim, e, NP, n);
-    high_node<MODE>(P, tb, N, prim + e * PRIM_VARS * NP, e, ec, n, qa, a);
+    high_node<MODE>(P, tb, N, prim + e * PRIM_VARS * NP, nullptr, e, ec, n, qa, a);
 }
 
-// Bytes of LDS stage_high_lds needs for one element of order N.
+// Bytes of LDS stage_high_lds needs for one element of order N: the partner
+// quantities, then one flag per line.
 inline size_t high_lds_bytes(int N)
 {
-    return sizeof(double) * PARTNER_VARS * (size_t)((N + 1) * (N + 1) * (N + 1));
+    const size_t nq = (size_t)(N + 1);
+    return sizeof(double) * PARTNER_VARS * nq * nq * nq + 3 * nq * nq;
 }
 
 // One workgroup per element (the grid has one block per element; blocks are
@@ -274,7 +302,7 @@ inline size_t high_lds_bytes(int N)
 template <int MODE, int THREADS, int WAVES>
 __global__ void __launch_bounds__(THREADS, WAVES) stage_high_lds(const StageParams P, int N)
 {
-    extern __shared__ double sprim[];  // [PARTNER_VARS][NP]
+    extern __shared__ double sprim[];  // [PARTNER_VARS][NP], then the line flags
     const int NQ = N + 1, NQ2 = NQ * NQ, NP = NQ2 * NQ;
     const int64_t e = xcd_remap(blockIdx.x, P.nblocks);
     int ec[3];
@@ -288,11 +316,30 @@ __global__ void __launch_bounds__(THREADS, WAVES) stage_high_lds(const StagePara
         store_partner(sprim + n, NP, nd, P.lnz_scale);
     }
     __syncthreads();
+    // lines whose extreme pair leaves the series range of a log-mean (the
+    // fused kernel's per-line test)
+    unsigned char *sflag = reinterpret_cast<unsigned char *>(sprim + PARTNER_VARS * NP);
+    for (int l = threadIdx.x; l < 3 * NQ2; l += THREADS) {
+        const int R = l / NQ2, li = l - R * NQ2;
+        const int n0 = R == 0 ? NQ * li : (R == 1 ? li % NQ + NQ2 * (li / NQ) : li);
+        const int st = R == 0 ? 1 : (R == 1 ? NQ : NQ2);
+        double rmn = sprim[n0], rmx = rmn, zmn = sprim[5 * NP + n0], zmx = zmn;
+        for (int t = 1; t < NQ; ++t) {
+            const double r = sprim[n0 + t * st], z = sprim[5 * NP + n0 + t * st];
+            rmn = fmin(rmn, r);
+            rmx = fmax(rmx, r);
+            zmn = fmin(zmn, z);
+            zmx = fmax(zmx, z);
+        }
+        sflag[l] = (!(rmx - rmn < LM_SQRT_EPS_LINE * (rmx + rmn)) ||
+                    !(zmx - zmn < LM_SQRT_EPS_LINE * (zmx + zmn))) ? 1 : 0;
+    }
+    __syncthreads();
     for (int n = threadIdx.x; n < NP; n += THREADS) {
         Cons qa;
         load_cons(P.q_in, e, NP, n, qa);
         const Node a = primitives(qa, phi_node(P, tb, ec[2], n / NQ2), gm1);
-        high_node<MODE>(P, tb, N, sprim, e, ec, n, qa, a);
+        high_node<MODE>(P, tb, N, sprim, sflag, e, ec, n, qa, a);
     }
 }
 
