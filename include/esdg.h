@@ -248,8 +248,10 @@ int esdg_pack_destroy(esdg_pack_t pack);
 /* Replace the member set: n meshes (same N <= 8, precision, epw, device), each
  * with q0[i], q1[i], dq[i] (device arrays of its state_len doubles, not
  * overlapping), time step dt[i], and parity[i] in {0, 1} naming the buffer
- * that holds its current state.  Synchronises the pack's stream; drops the
- * captured graph. */
+ * that holds its current state.  Waits for the pack's stream (a step in
+ * flight still reads the old table), then uploads the new table on that
+ * stream, ordered before the next step, from pinned host memory the pack
+ * owns; drops the captured graph. */
 int esdg_pack_set_members(esdg_pack_t pack, int32_t n, const esdg_mesh_t *meshes,
                           double *const *q0, double *const *q1, double *const *dq,
                           const double *dt, const int32_t *parity);
