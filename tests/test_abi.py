@@ -94,7 +94,10 @@ def test_invalid_arguments_fail_without_touching_the_device():
     assert esdg.lib.esdg_mesh_create(C.byref(d), None, C.byref(h)) == esdg.ESDG_EINVAL
     assert "warp" in esdg.last_error()
     assert esdg.lib.esdg_rhs(None, None, None, 0.0) == esdg.ESDG_EINVAL
-    assert esdg.lib.esdg_lgl_tables(9, None, None, None) == esdg.ESDG_EINVAL
+    assert esdg.lib.esdg_lgl_tables(4, None, None, None) == esdg.ESDG_EINVAL  # NULL outputs
+    buf = (C.c_double * 256)()
+    assert esdg.lib.esdg_lgl_tables(16, buf, buf, buf) == esdg.ESDG_EINVAL  # order above 15
+    assert "N=16" in esdg.last_error()
 
 
 def test_high_orders_are_fp64_affine_and_unpacked():
