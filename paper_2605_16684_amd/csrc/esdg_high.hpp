@@ -10,7 +10,9 @@
 // Coriolis source -- and writes R or applies the LSRK(5,4) stage update.
 // Each ordered pair is evaluated by both of its nodes (no flux-symmetry
 // saving: a thread owns one node's sum).  Log-means take the branch rule of
-// the fused kernel with logarithms only on the log branch.
+// the fused kernel, with the per-node logarithms on the log branch; in the
+// LDS kernel, waves whose lines all stay inside the series range take the
+// series-only flux.
 //
 // The partners' primitives (rho, u/2, p/2, rho/p: the quantities of the
 // two-point flux, Sec. 4.1) are formed once per node and per stage:
