@@ -47,6 +47,10 @@ from . import workloads as W
 
 FP64, FP32_MIXED = 0, 1
 
+# Packed stepping runs the fused kernels, which cover orders up to 8; the
+# server rejects requests of higher order.
+PACK_MAX_N = 8
+
 
 class NonPhysicalState(RuntimeError):
     """A member met rho <= 0, p <= 0 or NaN; it was evicted, the others run on."""
@@ -660,7 +664,7 @@ class Server:
             now = ex.now() - t_start
             while pending and pending[0].arrival <= now:
                 r = pending.pop(0)
-                if footprint_bytes(r) > self.budget:
+                if footprint_bytes(r) > self.budget or r.N > PACK_MAX_N:
                     rejected += 1
                     continue
                 queue.append(r)

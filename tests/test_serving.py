@@ -69,6 +69,14 @@ def test_requests_larger_than_budget_are_rejected_not_hung():
     assert st.n_rejected == 1 and st.n_completed == 4
 
 
+def test_requests_above_the_packable_order_are_rejected():
+    rs = _reqs(n=4)
+    high = S.Request(98, "bubble", (2, 2, 2), S.PACK_MAX_N + 1, S.FP64, 98, 2, 0.0)
+    budget = 100 * max(S.footprint_bytes(r) for r in rs + [high])
+    st = S.Server(budget, executor=S.FakeExecutor()).run(rs + [high], realtime=False)
+    assert st.n_rejected == 1 and st.n_completed == 4
+
+
 def test_failure_isolation():
     rs = _reqs(n=8)
     ex = S.FakeExecutor(fail_on={3})
