@@ -66,7 +66,7 @@ typedef struct esdg_mesh *esdg_mesh_t;
  *                affine box only, without elements-per-workgroup variants
  *                (epw must be 0) and not packable: one workgroup per element
  *                with the element's primitives in LDS where they fit the
- *                device's LDS per workgroup (N <= 12 on gfx950), else two
+ *                device's LDS per workgroup (N <= 14 on gfx950), else two
  *                launches per stage through a per-node buffer of 72 B held
  *                by the mesh (counted in its footprint)
  *   K[3]         elements per direction

@@ -17,9 +17,10 @@
 // The partners' primitives (rho, u/2, p/2, rho/p: the quantities of the
 // two-point flux, Sec. 4.1) are formed once per node and per stage:
 //   - stage_high_lds: one workgroup per element; the element's partner
-//     quantities (with the per-node logarithms, 64 B per node) go to LDS,
-//     then every thread sweeps its nodes' lines out of LDS.  Used where the
-//     element fits the workgroup's LDS (N <= 12 on gfx950's 160 KB).
+//     quantities (with the per-node logarithms up to N = 12: 64 B per node;
+//     without them, taken per pair on the log branch, at N = 13, 14: 48 B)
+//     go to LDS, then every thread sweeps its nodes' lines out of LDS.  Used
+//     where the element fits the workgroup's LDS (N <= 14 on gfx950).
 //   - prim_kernel + stage_high_kernel: otherwise, a per-mesh buffer
 //     prim[e][9][n] (72 B per node) written by a first launch and read by the
 //     node-per-thread launch through L2.
@@ -35,6 +36,10 @@ constexpr int HIGH_THREADS = 256;
 // Sec. 4.1), laid out [var][n] per element.  The prim buffer adds p/rho.
 constexpr int PARTNER_VARS = 8;
 constexpr int PRIM_VARS = 9;
+// Orders whose element, logarithms included, fits gfx950's 160 KB of LDS per
+// workgroup; up to N = 14 the LDS kernel holds the six quantities without the
+// logarithms and takes them per pair on the log branch.
+constexpr int HIGH_LDS_LOGS_MAX_N = 12;
 
 __device__ __forceinline__ double phi_node(const StageParams &P, const OrderTables &tb, int ez,
                                            int k)
@@ -46,9 +51,10 @@ __device__ __forceinline__ double phi_node(const StageParams &P, const OrderTabl
     return P.grav * (0.5 * (1.0 - s) * ZL + 0.5 * (1.0 + s) * ZR);
 }
 
-// The partner quantities of one node into an element block [var][NP].
+// The partner quantities of one node into an element block [var][NP], with
+// or without the two logarithms.
 __device__ __forceinline__ void store_partner(double *__restrict__ pb, int NP, const Node &nd,
-                                              double lnz_scale)
+                                              double lnz_scale, bool logs = true)
 {
     pb[0] = nd.r;
     pb[NP] = nd.h0;
@@ -56,8 +62,38 @@ __device__ __forceinline__ void store_partner(double *__restrict__ pb, int NP, c
     pb[3 * NP] = nd.h2;
     pb[4 * NP] = nd.hp;
     pb[5 * NP] = nd.z;
-    pb[6 * NP] = log(nd.r);
-    pb[7 * NP] = log(nd.z * lnz_scale);
+    if (logs) {
+        pb[6 * NP] = log(nd.r);
+        pb[7 * NP] = log(nd.z * lnz_scale);
+    }
+}
+
+// {{x}}_log and 1/{{x}}_log of one pair with the branch rule of the fused
+// kernel, logarithms (of x scaled by `scale`) taken here on the log branch.
+__device__ __forceinline__ double log_mean_lazy(double xa, double xb)
+{
+    const double d = xb - xa, s = xa + xb;
+    const bool ser = fabs(d) < LM_SQRT_EPS * s;
+    double den = s;
+    if (!ser) den = log(xb) - log(xa);
+    const double x = fdiv(d, den);
+    const double u = x * x;
+    return ser ? 0.5 * s * (1.0 - u * (S1 + u * (S2 + u * S3))) : x;
+}
+
+__device__ __forceinline__ double inv_log_mean_lazy(double xa, double xb, double scale)
+{
+    const double d = xb - xa, s = xa + xb;
+    const bool ser = fabs(d) < LM_SQRT_EPS * s;
+    double num = 1.0, den = s;
+    if (!ser) {
+        num = log(xb * scale) - log(xa * scale);
+        den = d;
+    }
+    const double x = fdiv(num, den);
+    const double dx = d * x;
+    const double u = dx * dx;
+    return ser ? 2.0 * x * (1.0 + u * (I1 + u * (I2 + u * I3))) : x;
 }
 
 // Primitives and logarithms of every node of q_in.
@@ -123,7 +159,7 @@ __device__ __forceinline__ int line_pos_node(int NQ, int i, int j, int k, int t)
 // flux (unscaled: the caller multiplies by 2/h_R).  lflag (or NULL) marks
 // the lines of the element that can reach the log branch of a log-mean;
 // where no line of the wave's nodes can, the pairs take the series-only flux.
-template <int R>
+template <int R, bool LOGS>
 __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTables &tb, int N,
                                            const double *__restrict__ pb,
                                            const unsigned char *lflag, const int ec[3], int i,
@@ -184,14 +220,20 @@ __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTabl
         }
     }
     const int na = line_pos_node<R>(NQ, i, j, k, ia);
-    const double lra = pb[6 * NP + na], lza = pb[7 * NP + na];
+    const double lra = LOGS ? pb[6 * NP + na] : 0.0, lza = LOGS ? pb[7 * NP + na] : 0.0;
     for (int t = 0; t < NQ; ++t) {
         if (t == ia) continue;
         const int nb = line_pos_node<R>(NQ, i, j, k, t);
         const Node b = load_partner(pb, NP, nb);
         const double phi_b = R == 2 ? phi_node(P, tb, ez, t) : phi_a;
-        const double rho_ln = log_mean(a.r, b.r, lra, pb[6 * NP + nb]);
-        const double izln = inv_log_mean(a.z, b.z, lza, pb[7 * NP + nb]);
+        double rho_ln, izln;
+        if constexpr (LOGS) {
+            rho_ln = log_mean(a.r, b.r, lra, pb[6 * NP + nb]);
+            izln = inv_log_mean(a.z, b.z, lza, pb[7 * NP + nb]);
+        } else {
+            rho_ln = log_mean_lazy(a.r, b.r);
+            izln = inv_log_mean_lazy(a.z, b.z, P.lnz_scale);
+        }
         const double hRa = hcomp<R>(a), hRb = hcomp<R>(b);
         const double frho = rho_ln * (hRa + hRb);
         double S[5];
@@ -216,7 +258,7 @@ __device__ __forceinline__ void node_terms(const StageParams &P, const OrderTabl
 
 // R at node n = (i, j, k) of element e (partner primitives in pb), then the
 // RHS store or the LSRK stage update of that node, and the flag check.
-template <int MODE>
+template <int MODE, bool LOGS = true>
 __device__ __forceinline__ void high_node(const StageParams &P, const OrderTables &tb, int N,
                                           const double *__restrict__ pb,
                                           const unsigned char *lflag, int64_t e,
@@ -228,13 +270,13 @@ __device__ __forceinline__ void high_node(const StageParams &P, const OrderTable
     double Rv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (P.mask & (TERM_VOL | TERM_FACE)) {
         double acc[5];
-        node_terms<0>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<0, LOGS>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[0] * acc[v];
-        node_terms<1>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<1, LOGS>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[1] * acc[v];
-        node_terms<2>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
+        node_terms<2, LOGS>(P, tb, N, pb, lflag, ec, i, j, k, a, qa, phi_a, acc);
 #pragma unroll
         for (int v = 0; v < 5; ++v) Rv[v] += P.two_h[2] * acc[v];
     }
@@ -289,24 +331,29 @@ __global__ void __launch_bounds__(HIGH_THREADS)
     high_node<MODE>(P, tb, N, prim + e * PRIM_VARS * NP, nullptr, e, ec, n, qa, a);
 }
 
+// Partner quantities per node that stage_high_lds holds in LDS at order N.
+__host__ __device__ inline int high_lds_vars(int N)
+{
+    return N <= HIGH_LDS_LOGS_MAX_N ? PARTNER_VARS : PARTNER_VARS - 2;
+}
+
 // Bytes of LDS stage_high_lds needs for one element of order N: the partner
 // quantities, then one flag per line.
 inline size_t high_lds_bytes(int N)
 {
     const size_t nq = (size_t)(N + 1);
-    return sizeof(double) * PARTNER_VARS * nq * nq * nq + 3 * nq * nq;
+    return sizeof(double) * high_lds_vars(N) * nq * nq * nq + 3 * nq * nq;
 }
 
-// One workgroup per element (the grid has one block per element; blocks are
-// dealt to the XCDs so that each walks a contiguous range of elements).  The
-// element's primitives are formed once into LDS, then each thread finishes
-// its nodes n = tid, tid + THREADS, ...
-template <int MODE, int THREADS, int WAVES>
-__global__ void __launch_bounds__(THREADS, WAVES) stage_high_lds(const StageParams P, int N)
+// One workgroup per element: the element's partner quantities are formed
+// once into LDS (with the logarithms when LOGS), the lines that can reach the
+// log branch are marked, then each thread finishes its nodes n = tid,
+// tid + THREADS, ...
+template <int MODE, int THREADS, bool LOGS>
+__device__ __forceinline__ void stage_high_lds_body(const StageParams &P, int N, int64_t e,
+                                                    double *sprim)
 {
-    extern __shared__ double sprim[];  // [PARTNER_VARS][NP], then the line flags
     const int NQ = N + 1, NQ2 = NQ * NQ, NP = NQ2 * NQ;
-    const int64_t e = xcd_remap(blockIdx.x, P.nblocks);
     int ec[3];
     elem_coords(P, e, ec);
     const OrderTables &tb = c_tab[N - 1];
@@ -315,12 +362,12 @@ __global__ void __launch_bounds__(THREADS, WAVES) stage_high_lds(const StagePara
         Cons c;
         load_cons(P.q_in, e, NP, n, c);
         const Node nd = primitives(c, phi_node(P, tb, ec[2], n / NQ2), gm1);
-        store_partner(sprim + n, NP, nd, P.lnz_scale);
+        store_partner(sprim + n, NP, nd, P.lnz_scale, LOGS);
     }
     __syncthreads();
     // lines whose extreme pair leaves the series range of a log-mean (the
     // fused kernel's per-line test)
-    unsigned char *sflag = reinterpret_cast<unsigned char *>(sprim + PARTNER_VARS * NP);
+    unsigned char *sflag = reinterpret_cast<unsigned char *>(sprim + high_lds_vars(N) * NP);
     for (int l = threadIdx.x; l < 3 * NQ2; l += THREADS) {
         const int R = l / NQ2, li = l - R * NQ2;
         const int n0 = R == 0 ? NQ * li : (R == 1 ? li % NQ + NQ2 * (li / NQ) : li);
@@ -341,8 +388,21 @@ __global__ void __launch_bounds__(THREADS, WAVES) stage_high_lds(const StagePara
         Cons qa;
         load_cons(P.q_in, e, NP, n, qa);
         const Node a = primitives(qa, phi_node(P, tb, ec[2], n / NQ2), gm1);
-        high_node<MODE>(P, tb, N, sprim, sflag, e, ec, n, qa, a);
+        high_node<MODE, LOGS>(P, tb, N, sprim, sflag, e, ec, n, qa, a);
     }
+}
+
+// The grid has one block per element; blocks are dealt to the XCDs so that
+// each walks a contiguous range of elements.
+template <int MODE, int THREADS, int WAVES>
+__global__ void __launch_bounds__(THREADS, WAVES) stage_high_lds(const StageParams P, int N)
+{
+    extern __shared__ double sprim[];  // [high_lds_vars(N)][NP], then the line flags
+    const int64_t e = xcd_remap(blockIdx.x, P.nblocks);
+    if (N <= HIGH_LDS_LOGS_MAX_N)
+        stage_high_lds_body<MODE, THREADS, true>(P, N, e, sprim);
+    else
+        stage_high_lds_body<MODE, THREADS, false>(P, N, e, sprim);
 }
 
 }  // namespace esdg

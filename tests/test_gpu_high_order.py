@@ -1,5 +1,6 @@
-"""Parity of the high-order path (N = 9..15, node-per-thread kernels) with the
-CPU oracle, through the C ABI.
+"""Parity of the high-order path (N = 9..15, node-per-thread kernels: the
+element in LDS with the logarithms up to N = 12 and without them at N = 13,
+14, the prim buffer at N = 15) with the CPU oracle, through the C ABI.
 
 Same bars as the fused path (tests/_parity.py): per conserved variable the
 RHS error is at most 2e-14 of the gross term scale and max(1e-12, 64 eps
@@ -84,6 +85,7 @@ def test_high_order_term_split_parity(mask):
 
 
 @pytest.mark.parametrize("N,K,kind", [(9, (2, 2, 2), "bubble"), (12, (2, 1, 2), "iso_pert"),
+                                      (13, (1, 1, 2), "iso_pert"), (14, (1, 1, 2), "bubble"),
                                       (15, (1, 1, 2), "iso_pert")])
 def test_high_order_lsrk_steps_parity(N, K, kind):
     """Ten LSRK steps (eager, dq starting as NaN) and the graph-replayed run
@@ -95,7 +97,7 @@ def test_high_order_lsrk_steps_parity(N, K, kind):
         spec = W.MeshSpec(N, K, *_BOX, (1, 0, 0), coriolis_f=1e-4, surface_flux=2)
     om = _oracle_mesh(spec)
     q0 = W.make_state(kind, om.coords(), spec, seed=7)
-    dt = om.cfl_dt(q0, 0.5)
+    dt = om.cfl_dt(q0, 0.25)  # CFL 0.5 is unstable at high orders
     n = 10
     q_or = om.run(q0, dt, n)
     _, g0 = om.rhs(q0, gross=True)
@@ -119,7 +121,7 @@ def test_high_order_conservation_over_steps():
     spec = W.MeshSpec(11, (2, 2, 1), *_BOX, (1, 1, 0), coriolis_f=1e-4, surface_flux=2)
     om = _oracle_mesh(spec)
     q0 = _with_jumps(W.state_iso_pert(om.coords(), spec, seed=9), 9)
-    dt = om.cfl_dt(q0, 0.5)
+    dt = om.cfl_dt(q0, 0.25)  # CFL 0.5 is unstable at high orders
     m = esdg.Mesh(spec)
     qg = torch.from_numpy(q0).cuda()
     dq = torch.zeros_like(qg)
