@@ -324,6 +324,46 @@ def surface_block(esdg, torch, perfmodel, wl, spec, q, dt, steps, epw, value, t_
 CURVED_WARP = (0.05, 0.04, 0.03)
 
 
+def high_order_block(esdg, W, torch, steps=10):
+    """Orders above the fused kernel's: the perturbed isothermal boxes of
+    1 km elements at N = 12 (node-per-thread kernel with the element in LDS)
+    and N = 15 (primitives buffer), CFL 0.25, event-timed LSRK steps and RHS
+    launches."""
+    out = {}
+    for key in ("h12", "h15"):
+        wl = W.WORKLOADS[key]
+        spec = wl.mesh
+        m = esdg.Mesh(spec)
+        q = W.make_state(wl.kind, m.coords(), spec, seed=1).contiguous()
+        dq = torch.zeros_like(q)
+        dt = m.cfl_dt(q, wl.cfl)
+        m.lsrk_run(q, dq, dt, 2)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        m.lsrk_run(q, dq, dt, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r = torch.empty_like(q)
+        m.rhs(q, r)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            m.rhs(q, r)
+        e1.record()
+        torch.cuda.synchronize()
+        m.check()
+        out[wl.name] = {"N": spec.N, "nodes": m.n_nodes, "cfl": wl.cfl, "steps": steps,
+                        "ms_per_step": ms, "dof_rhs_per_s": m.n_nodes * 5.0 / (ms * 1e-3),
+                        "rhs_launch_ms": e0.elapsed_time(e1) / 10,
+                        "kernels": "node-per-thread stage, element in LDS" if spec.N <= 14
+                        else "primitives buffer + node-per-thread stage"}
+        m.close()
+        del q, dq, r
+    return out
+
+
 def curved_block(esdg, W, torch, perfmodel, wl, steps, value, cpu_seconds):
     """The same workload on the warped box (curved hexahedra, per-node
     metric terms): whole LSRK(5,4) steps and RHS launches, with the curved
@@ -422,6 +462,8 @@ def main():
     ap.add_argument("--no-symmetry", action="store_true",
                     help="skip the long sharp/smooth bubble runs with the symmetry defect")
     ap.add_argument("--symmetry-steps", type=int, default=1000)
+    ap.add_argument("--no-high-order", action="store_true",
+                    help="skip the N=12 and N=15 boxes of the node-per-thread kernels")
     ap.add_argument("--no-serving", action="store_true", help="skip the ensemble serving run")
     ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--surface", default="rusanov", choices=("rusanov", "matrix", "ec"),
@@ -603,6 +645,10 @@ def main():
         log("[bench] FP64 vs FP32-mixed ...")
         out["precision"] = precision_block(esdg, W, torch, steps=args.precision_steps,
                                            workload=args.precision_workload)
+        torch.cuda.empty_cache()
+    if not args.no_high_order:
+        log("[bench] orders 12 and 15 ...")
+        out["high_order"] = high_order_block(esdg, W, torch)
         torch.cuda.empty_cache()
     if not args.no_symmetry:
         log("[bench] sharp and smooth bubbles, symmetry defect ...")
